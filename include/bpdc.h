@@ -1,0 +1,194 @@
+/*
+ * bpdc.h -- C ABI of the MI355X (gfx950) BP+DC decoder library, libbpdc.so.
+ *
+ * BP+DC (degeneracy cutting, arXiv 2510.08695): scaled min-sum belief
+ * propagation on the Tanner graph of a parity-check matrix H (H_Z, or a
+ * detector check matrix), then -- only for shots whose first pass did not
+ * reproduce the syndrome -- every row of a degeneracy matrix D (H_X, or a
+ * detector degeneracy matrix) nominates the variable of highest posterior LLR
+ * (= lowest posterior error probability) in its support, the nominees are cut
+ * (prior probability 0), and BP is run again (Algorithm 1 with the cut of
+ * Algorithm 2, Sec. III.A; the detector-error-model form of Sec. IV.B).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns bpdc_status; 0 (BPDC_OK) is success.  Nothing
+ *    throws across the ABI.  On a non-OK return, bpdc_last_error() gives a
+ *    thread-local message.
+ *  - Pointers named h_* are host memory, d_* are device memory on the
+ *    current HIP device.  The caller owns every h_* and d_* buffer; the
+ *    library owns the handles and its own device copies of H, D and the priors.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is enqueued on it asynchronously; the only
+ *    host-synchronising calls are bpdc_code_create / bpdc_plan_create.
+ *  - Bit vectors are packed little-endian: bit j of a vector is bit (j & 63)
+ *    of 64-bit word (j >> 6).  Padding bits are ignored on input and written
+ *    as 0 on output.
+ *  - Results depend only on (code, params, syndrome, seed, shot_offset + index
+ *    of the shot), never on the kernel variant, tile shape, batch split or
+ *    stream.
+ */
+#ifndef BPDC_H
+#define BPDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bpdc_status;
+enum {
+  BPDC_OK = 0,
+  BPDC_ERR_INVALID_ARG = 1, /* null pointer, negative size, bad CSR, p outside (0,1), ... */
+  BPDC_ERR_UNSUPPORTED = 2, /* degree above the compiled limit, kernel variant not available */
+  BPDC_ERR_WORKSPACE = 3,   /* workspace missing or smaller than bpdc_workspace_size() */
+  BPDC_ERR_HIP = 4,         /* a HIP runtime call failed (message in bpdc_last_error) */
+  BPDC_ERR_OOM = 5          /* device allocation failed */
+};
+
+/* Second-pass prior (Sec. III.B): the channel prior p (BB codes) or the
+ * first-pass posteriors (surface / toric codes).  Cut variables always get
+ * prior probability 0 (Algorithm 2). */
+enum { BPDC_PRIOR_CHANNEL = 0, BPDC_PRIOR_POSTERIOR = 1 };
+
+/* Tie-break among DC candidates of equal posterior (Sec. III.A: "selected at
+ * random"): a counter-based SplitMix64 hash of (seed, shot, row), or the
+ * lowest column index. */
+enum { BPDC_TIE_HASH = 0, BPDC_TIE_LOWEST_INDEX = 1 };
+
+/* Kernel family of a plan. */
+enum {
+  BPDC_KERNEL_AUTO = 0,  /* autotuner picks among the fused variants */
+  BPDC_KERNEL_PLAIN = 1, /* one launch per BP phase per iteration, messages in HBM */
+  BPDC_KERNEL_LANE = 2,  /* fused persistent BP->DC->BP, one shot per lane, code-specialised */
+  BPDC_KERNEL_GROUP = 3  /* fused persistent BP->DC->BP, shots per workgroup, state in LDS */
+};
+
+/* Binary matrix in CSR form (host memory): 0-based column indices, sorted and
+ * unique within each row.  row_ptr has rows + 1 entries. */
+typedef struct {
+  int32_t rows, cols;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+} bpdc_csr;
+
+/* Decoder parameters (the paper leaves the min-sum scale, the saturation and
+ * the tie tolerance open; these are the knobs). */
+typedef struct {
+  int32_t max_iter[2];       /* T before DC, T after DC (each >= 1) */
+  float alpha;               /* min-sum scale: r = alpha * min |q| */
+  int32_t second_pass_prior; /* BPDC_PRIOR_* */
+  int32_t stop_on_converge;  /* 1: stop a pass once H e = s (Sec. II.C); 0: run all iterations */
+  float llr_sat;             /* messages and reported posteriors saturate at +-llr_sat (> 0, finite) */
+  float tie_eps;             /* DC tie set: L_i >= L_max - tie_eps * max(1, |L_max|) (>= 0) */
+  int32_t tie_break;         /* BPDC_TIE_* */
+  uint64_t seed;             /* tie-break hash seed */
+} bpdc_params;
+
+typedef struct bpdc_code_s* bpdc_code; /* immutable after creation */
+typedef struct bpdc_plan_s* bpdc_plan; /* launch configuration for one or more codes */
+
+/* Load a decoding problem: Tanner graph H (m x n), degeneracy matrix D
+ * (m' x n, same n) and per-column prior error probabilities h_priors[n], each
+ * in (0, 1).  The prior LLRs log((1-p)/p) are evaluated in double and rounded
+ * once to float.  Copies everything to the current device; synchronous.
+ * Row degree of H is limited to 32, column degree of H to 16, row degree of D
+ * to 32 (BPDC_ERR_UNSUPPORTED otherwise). */
+bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double* h_priors,
+                             bpdc_code* out);
+bpdc_status bpdc_code_destroy(bpdc_code code);
+/* Sizes of a code: n columns, m rows of H, m' rows of D, E edges of H. */
+bpdc_status bpdc_code_info(bpdc_code code, int32_t* n, int32_t* m, int32_t* md, int32_t* edges);
+
+/* Build a plan for `ncodes` codes (they stay owned by the caller and must
+ * outlive the plan).  `kernel` is a BPDC_KERNEL_* value; AUTO times the
+ * available fused variants on the device and keeps the fastest (synchronous).
+ * BPDC_ERR_UNSUPPORTED if the requested variant cannot run a code. */
+bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
+                             int32_t kernel, bpdc_plan* out);
+bpdc_status bpdc_plan_destroy(bpdc_plan plan);
+/* The variant and tile a plan chose for code `code`: kernel (BPDC_KERNEL_*),
+ * shots per workgroup, threads per workgroup. */
+bpdc_status bpdc_plan_info(bpdc_plan plan, int32_t code, int32_t* kernel, int32_t* shots_per_wg,
+                           int32_t* threads_per_wg);
+
+/* Device workspace (bytes) that bpdc_decode needs for a batch of B shots of
+ * code `code` (bpdc_decode_multi: pass code = -1 and the total batch). */
+bpdc_status bpdc_workspace_size(bpdc_plan plan, int32_t code, int64_t B, size_t* bytes);
+
+/* Decode B shots of code `code` (index into the plan's code list).
+ *   d_syn   [B][ceil(m/64)] uint64 packed syndromes (input)
+ *   d_corr  [B][ceil(n/64)] uint64 packed corrections e_hat (output; cut columns are 0)
+ *   d_flags [B] uint8: bit 0 = H e_hat = s, bit 1 = DC ran (output)
+ *   d_post  [B][n] float posterior LLRs of the final pass, saturated, +inf on cut
+ *           columns (optional, may be NULL)
+ *   d_cut   [B][ceil(n/64)] uint64 cut set, all zero where DC did not run (optional)
+ *   d_iters [B][2] int16 iterations executed before / after DC (optional)
+ *   shot_offset: global index of shot 0 (tie-break hash counter)
+ *   d_ws, ws_bytes: workspace of at least bpdc_workspace_size() bytes. */
+bpdc_status bpdc_decode(bpdc_plan plan, int32_t code, const uint64_t* d_syn, int64_t B,
+                        int64_t shot_offset, uint64_t* d_corr, uint8_t* d_flags, float* d_post,
+                        uint64_t* d_cut, int16_t* d_iters, void* d_ws, size_t ws_bytes,
+                        void* stream);
+
+/* Decode a mixed batch of B shots over all codes of the plan in one persistent
+ * launch.  Shot b belongs to code d_code_of_shot[b]; its syndrome starts at
+ * word d_syn_off[b] of d_syn and its correction at word d_corr_off[b] of d_corr.
+ * d_flags [B], d_iters [B][2] (optional) as in bpdc_decode.  The tie-break
+ * counter of shot b is shot_offset + b. */
+bpdc_status bpdc_decode_multi(bpdc_plan plan, const int32_t* d_code_of_shot, const uint64_t* d_syn,
+                              const int64_t* d_syn_off, uint64_t* d_corr, const int64_t* d_corr_off,
+                              uint8_t* d_flags, int16_t* d_iters, int64_t B, int64_t shot_offset,
+                              void* d_ws, size_t ws_bytes, void* stream);
+
+/* Capture bpdc_decode_multi with fixed buffers into a HIP graph owned by the
+ * plan; bpdc_graph_launch replays it on `stream`. */
+bpdc_status bpdc_graph_capture_multi(bpdc_plan plan, const int32_t* d_code_of_shot,
+                                     const uint64_t* d_syn, const int64_t* d_syn_off,
+                                     uint64_t* d_corr, const int64_t* d_corr_off, uint8_t* d_flags,
+                                     int16_t* d_iters, int64_t B, int64_t shot_offset, void* d_ws,
+                                     size_t ws_bytes, void* stream);
+bpdc_status bpdc_graph_launch(bpdc_plan plan, void* stream);
+
+/* Weighted min-sum (learned per-edge scales, one set per pass): the forward
+ * runs T1 iterations, DC on shots whose first pass failed, then T2 iterations,
+ * with no early stop, and stores check-state checkpoints every `ckpt_every`
+ * iterations for the backward.
+ *   d_w      [2][E] float scales in CSR edge order of H (pass 1, pass 2)
+ *   d_post   [2][B][n] float posteriors at the end of each pass (pass-2 rows
+ *            of shots without DC are copies of pass 1)
+ *   d_cut    [B][ceil(n/64)] uint64 cut set (output, held fixed in backward)
+ *   d_ckpt   checkpoint buffer of bpdc_wms_ckpt_size() bytes. */
+bpdc_status bpdc_wms_ckpt_size(bpdc_plan plan, int32_t code, int64_t B, int32_t ckpt_every,
+                               size_t* bytes);
+bpdc_status bpdc_wms_forward(bpdc_plan plan, int32_t code, const float* d_w, const uint64_t* d_syn,
+                             int64_t B, int64_t shot_offset, int32_t ckpt_every, float* d_post,
+                             uint64_t* d_cut, uint8_t* d_flags, void* d_ckpt, size_t ckpt_bytes,
+                             void* stream);
+/* Adjoint of bpdc_wms_forward: given dLoss/dpost [2][B][n], accumulate
+ * dLoss/dw into d_grad_w [2][E] (the caller zeroes it).  The cut is constant
+ * (piecewise differentiation through min and sign; saturated messages have
+ * zero derivative). */
+bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
+                              const uint64_t* d_syn, int64_t B, int32_t ckpt_every,
+                              const float* d_grad_post, const uint64_t* d_cut,
+                              const uint8_t* d_flags, const void* d_ckpt, size_t ckpt_bytes,
+                              float* d_grad_w, void* stream);
+
+/* Compile, or find in the on-disk kernel cache, the code-specialised lane
+ * kernel for (H, D) without touching a GPU (host-only; hipRTC).  The cache
+ * directory is $BPDC_CACHE_DIR, else kcache/ beside libbpdc.so.  posterior =
+ * 1 for plans with BPDC_PRIOR_POSTERIOR.  BPDC_ERR_UNSUPPORTED if the code is
+ * too large for the lane kernel. */
+bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior);
+
+const char* bpdc_status_string(bpdc_status status);
+const char* bpdc_last_error(void);
+/* Library build identifier (the kernel variants compiled in). */
+const char* bpdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPDC_H */

@@ -1,0 +1,333 @@
+// Fused persistent BP -> DC -> BP kernel with one workgroup per shot and the
+// shot's whole state in LDS: any code size up to the LDS of one workgroup,
+// any mix of codes in one launch.
+//
+// A workgroup takes the next shot from a global counter (shots of a mixed
+// batch are first grouped by code, largest codes first, so that long shots
+// start early and consecutive shots of a workgroup share the code's index
+// arrays in cache).  Per iteration (flooding schedule, Sec. II.C) it runs
+//   check phase  : one thread per check: q = sat(L_v - r_old) for each edge,
+//                  new (alpha*min1, alpha*min2, argmin, r-sign bits);
+//   variable phase: one thread per column: L_v = prior + sum r (ascending
+//                  check order), +inf on cut columns (Algorithm 2);
+//   stop phase   : one thread per check: parity of [L <= 0] over the check
+//                  against the syndrome bit (H e = s);
+// with a workgroup barrier between phases.  After a failed first pass it runs
+// degeneracy cutting (Sec. III.A) with one thread per row of D and the second
+// pass, then writes the packed correction.  The arithmetic order is that of
+// every other decoder of the library, so results are bit-identical.
+#include "internal.h"
+// after the HIP runtime header: bpdc_device.h itself includes nothing
+#include "bpdc_device.h"
+
+namespace bpdc {
+
+// Device-side description of one code of a (multi-code) plan.
+struct GCode {
+  int n, m, md;
+  int posterior;  // unused per code (plan-wide), kept for alignment
+  const int32_t* h_row_ptr;
+  const int32_t* h_col;
+  const int32_t* h_col_ptr;
+  const int32_t* h_col_edge;
+  const int32_t* h_edge_row;
+  const int32_t* d_row_ptr;
+  const int32_t* d_col;
+  const float* lam;
+};
+
+namespace {
+
+using bpdc_dev::u32;
+using bpdc_dev::u64;
+
+struct GArgs {
+  const GCode* codes;
+  const int32_t* code_of_shot;  // null: every shot is code 0
+  const int32_t* order;         // null: identity processing order
+  const uint64_t* syn;
+  const int64_t* syn_off;       // null: b * ceil(m/64)
+  uint64_t* corr;
+  const int64_t* corr_off;      // null: b * ceil(n/64)
+  uint8_t* flags;
+  float* post;                  // single-code only (may be null)
+  uint64_t* cut;                // single-code only (may be null)
+  int16_t* iters;
+  int64_t B;
+  int64_t shot_offset;
+  unsigned long long* queue;
+  KParams p;
+};
+
+// Packed per-check info: low bits r-sign of each edge, top bits argmin position.
+template <class InfoT>
+struct InfoTraits;
+template <>
+struct InfoTraits<uint16_t> {
+  static constexpr int kPosShift = 12;
+  static constexpr u32 kSignMask = 0xFFFu;
+};
+template <>
+struct InfoTraits<u32> {
+  static constexpr int kPosShift = 27;
+  static constexpr u32 kSignMask = 0x7FFFFFFu;
+};
+
+template <class InfoT>
+__device__ __forceinline__ float decode_r(float a1, float a2, InfoT info, int k) {
+  const u32 w = (u32)info;
+  const int amin = (int)(w >> InfoTraits<InfoT>::kPosShift);
+  const float mag = (amin == k) ? a2 : a1;
+  return ((w >> k) & 1u) ? -mag : mag;
+}
+
+template <class InfoT>
+__global__ void __launch_bounds__(1024) k_group(GArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ long long sIdx;
+  __shared__ int sUnsat;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+  const KParams& P = a.p;
+  const float LS = P.lsat;
+  const float INF = __builtin_huge_valf();
+
+  for (;;) {
+    if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
+    __syncthreads();
+    const long long idx = sIdx;
+    __syncthreads();
+    if (idx >= a.B) break;
+    const long long b = a.order ? (long long)a.order[idx] : idx;
+    const int ci = a.code_of_shot ? a.code_of_shot[b] : 0;
+    const GCode C = a.codes[ci];
+    const int n = C.n, m = C.m;
+    const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
+    // LDS carve for this code
+    float* L = (float*)smem;                       // [n]
+    float* A1 = L + n;                             // [m]
+    float* A2 = A1 + m;                            // [m]
+    u32* cutw = (u32*)(A2 + m);                    // [ceil(n/32)]
+    u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
+    float* lam2 = (float*)(synw + ((m + 31) >> 5));  // [n] (posterior second pass)
+    InfoT* info = (InfoT*)(lam2 + (P.second_pass_posterior ? n : 0));  // [m]
+
+    const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
+    for (int w = tid; w < ((m + 31) >> 5); w += nt) {
+      const uint64_t x = sp[w >> 1];
+      synw[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
+    }
+    for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
+
+    int it[2] = {0, 0};
+    bool conv = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int T = pass ? P.T2 : P.T1;
+      const bool use_lam2 = pass == 1 && P.second_pass_posterior;
+      for (int c = tid; c < m; c += nt) {
+        A1[c] = 0.0f;
+        A2[c] = 0.0f;
+        info[c] = (InfoT)0;
+      }
+      __syncthreads();
+      int t = 0;
+      for (;;) {
+        // ---- variable phase: L = prior + sum of r (all zero at t = 0) ----
+        for (int v = tid; v < n; v += nt) {
+          float Lv;
+          if (use_lam2) Lv = lam2[v];
+          else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
+          if (Lv != INF) {
+            for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) {
+              const int e = C.h_col_edge[k];
+              const int c = C.h_edge_row[e];
+              Lv = Lv + decode_r<InfoT>(A1[c], A2[c], info[c], e - C.h_row_ptr[c]);
+            }
+          }
+          L[v] = Lv;
+        }
+        if (tid == 0) sUnsat = 0;
+        __syncthreads();
+        if (t >= 1) {
+          // ---- stop phase: H e = s with e = [L <= 0] ----
+          int bad = 0;
+          for (int c = tid; c < m; c += nt) {
+            u32 par = (synw[c >> 5] >> (c & 31)) & 1u;
+            for (int e = C.h_row_ptr[c]; e < C.h_row_ptr[c + 1]; ++e) par ^= (L[C.h_col[e]] <= 0.0f) ? 1u : 0u;
+            bad |= (int)par;
+          }
+          if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat, 1);
+          __syncthreads();
+          const bool ok = sUnsat == 0;
+          if ((P.stop && ok) || t >= T) {
+            conv = ok;
+            it[pass] = t;
+            break;
+          }
+        }
+        // ---- check phase: next check state from q = sat(L - r_old) ----
+        for (int c = tid; c < m; c += nt) {
+          const int e0 = C.h_row_ptr[c], d = C.h_row_ptr[c + 1] - e0;
+          const float a1o = A1[c], a2o = A2[c];
+          const InfoT io = info[c];
+          float m1 = LS, m2 = LS;
+          int amin = 0;
+          u32 sb = 0;
+          for (int k = 0; k < d; ++k) {
+            const float q = bpdc_dev::sat(L[C.h_col[e0 + k]] - decode_r<InfoT>(a1o, a2o, io, k), LS);
+            const float aq = fabsf(q);
+            if (aq < m1) {
+              m2 = m1;
+              m1 = aq;
+              amin = k;
+            } else if (aq < m2) {
+              m2 = aq;
+            }
+            sb |= ((q < 0.0f) ? 1u : 0u) << k;
+          }
+          const u32 par = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
+          const u32 rb = par ? (sb ^ ((1u << d) - 1u)) : sb;
+          A1[c] = P.alpha * m1;
+          A2[c] = P.alpha * m2;
+          info[c] = (InfoT)(rb | ((u32)amin << InfoTraits<InfoT>::kPosShift));
+        }
+        __syncthreads();
+        ++t;
+      }
+      if (pass == 1 || conv) break;
+      // ---- degeneracy cutting (first pass failed) ----
+      for (int h = tid; h < C.md; h += nt) {
+        const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
+        if (deg == 0) continue;
+        int cols[32];
+        float vals[32];
+        for (int k = 0; k < deg; ++k) {
+          cols[k] = C.d_col[e0 + k];
+          vals[k] = bpdc_dev::sat(L[cols[k]], LS);
+        }
+        const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, P.tie_eps, P.tie_lowest, P.seed,
+                                               (u64)(a.shot_offset + b), (u64)h);
+        atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+      }
+      __syncthreads();
+      if (P.second_pass_posterior)
+        for (int v = tid; v < n; v += nt)
+          lam2[v] = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : bpdc_dev::sat(L[v], LS);
+      __syncthreads();
+    }
+    // ---- outputs ----
+    const bool dc = it[1] > 0;
+    uint64_t* cp = a.corr + (a.corr_off ? a.corr_off[b] : b * nw64);
+    for (int w = wave; w < nw64; w += nwaves) {
+      const int v = w * 64 + lane;
+      const u64 word = __ballot(v < n && L[v] <= 0.0f);
+      if (lane == 0) cp[w] = word;
+      if (a.cut) {
+        const u32 lo = cutw[2 * w];
+        const u32 hi = (2 * w + 1 < ((n + 31) >> 5)) ? cutw[2 * w + 1] : 0u;
+        if (lane == 0) a.cut[b * nw64 + w] = dc ? (((u64)hi << 32) | lo) : 0ull;
+      }
+    }
+    if (a.post)
+      for (int v = tid; v < n; v += nt) {
+        const float x = L[v];
+        a.post[b * n + v] = (x == INF) ? x : bpdc_dev::sat(x, LS);
+      }
+    if (tid == 0) {
+      a.flags[b] = (uint8_t)((conv ? 1 : 0) | (dc ? 2 : 0));
+      if (a.iters) {
+        a.iters[2 * b] = (int16_t)it[0];
+        a.iters[2 * b + 1] = (int16_t)it[1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Processing order of a mixed batch: shots grouped by code, codes by
+// descending column count (counting sort; order within a code is arbitrary,
+// results do not depend on it).
+__global__ void k_order_hist(const int32_t* code_of_shot, int64_t B, unsigned* hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) atomicAdd(&hist[code_of_shot[i]], 1u);
+}
+__global__ void k_order_scan(const int32_t* rank_of_code, const int32_t* code_by_rank, int ncodes,
+                             const unsigned* hist, unsigned* base) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned s = 0;
+  for (int r = 0; r < ncodes; ++r) {
+    const int c = code_by_rank[r];
+    base[c] = s;
+    s += hist[c];
+  }
+  (void)rank_of_code;
+}
+__global__ void k_order_scatter(const int32_t* code_of_shot, int64_t B, unsigned* base, int32_t* order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) order[atomicAdd(&base[code_of_shot[i]], 1u)] = (int32_t)i;
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+size_t group_lds_bytes_nm(int n, int m, bool posterior, bool info16) {
+  size_t words = (size_t)n + 2 * (size_t)m + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
+  return words * 4 + (size_t)m * (info16 ? 2 : 4) + 16;
+}
+
+hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
+                        const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
+                        const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
+                        int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
+                        size_t lds, bool info16, unsigned long long* queue, hipStream_t stream) {
+  GArgs a;
+  a.codes = (const GCode*)d_codes;
+  a.code_of_shot = code_of_shot;
+  a.order = order;
+  a.syn = syn;
+  a.syn_off = syn_off;
+  a.corr = corr;
+  a.corr_off = corr_off;
+  a.flags = flags;
+  a.post = post;
+  a.cut = cut;
+  a.iters = iters;
+  a.B = B;
+  a.shot_offset = shot_offset;
+  a.queue = queue;
+  a.p = p;
+  hipError_t e = fill_u64((uint64_t*)queue, 0, 1, stream);
+  if (e != hipSuccess) return e;
+  if (info16) hipLaunchKernelGGL(k_group<uint16_t>, dim3(grid), dim3(threads), lds, stream, a);
+  else hipLaunchKernelGGL(k_group<u32>, dim3(grid), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+// Allow the group kernels up to `max_lds` bytes of dynamic LDS (once per
+// process and device), then report how many workgroups of `threads` threads
+// and `lds` bytes fit on a compute unit.
+int group_occupancy(int threads, size_t lds, bool info16, int max_lds) {
+  hipFuncSetAttribute((const void*)k_group<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  hipFuncSetAttribute((const void*)k_group<u32>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  int nb = 0;
+  if (info16) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds);
+  else hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds);
+  return nb;
+}
+
+hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,
+                       unsigned* hist, unsigned* base, int32_t* order, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_u32, dim3((ncodes + 255) / 256), dim3(256), 0, stream, hist, ncodes);
+  const unsigned g = (unsigned)((B + 255) / 256);
+  if (B > 0) hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, stream, code_of_shot, B, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, stream, (const int32_t*)nullptr, code_by_rank, ncodes,
+                     hist, base);
+  if (B > 0) hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, stream, code_of_shot, B, base, order);
+  return hipGetLastError();
+}
+
+}  // namespace bpdc

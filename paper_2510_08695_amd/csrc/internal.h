@@ -1,0 +1,95 @@
+// Internal interfaces between the host runtime (runtime.cpp) and the kernels
+// of libbpdc.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bpdc {
+
+// A code resident on the device: Tanner graph H in CSR and CSC form, the
+// degeneracy matrix D in CSR form and the prior LLRs (float, rounded once
+// from double).  Edge e of H is its CSR position; the CSC lists per column
+// the CSR positions of its edges in ascending row order.
+struct DevCode {
+  int n = 0, m = 0, md = 0, E = 0, dnnz = 0;
+  int max_row_deg = 0, max_col_deg = 0, max_drow_deg = 0;
+  int32_t* h_row_ptr = nullptr;  // [m+1]
+  int32_t* h_col = nullptr;      // [E]
+  int32_t* h_col_ptr = nullptr;  // [n+1]
+  int32_t* h_col_edge = nullptr; // [E] CSR edge ids, per column ascending row
+  int32_t* h_edge_row = nullptr; // [E] row of each edge
+  int32_t* d_row_ptr = nullptr;  // [md+1]
+  int32_t* d_col = nullptr;      // [dnnz]
+  float* lam = nullptr;          // [n]
+};
+
+// Runtime decoder parameters as the kernels see them.
+struct KParams {
+  int T1, T2;
+  float alpha, lsat, tie_eps;
+  int second_pass_posterior;
+  int stop;
+  int tie_lowest;
+  unsigned long long seed;
+};
+
+// Output / input buffers of one single-code decode.
+struct DecodeIO {
+  const uint64_t* syn;
+  int64_t B;
+  int64_t shot_offset;
+  uint64_t* corr;
+  uint8_t* flags;
+  float* post;
+  uint64_t* cut;
+  int16_t* iters;
+};
+
+// Plain decoder: one launch per phase per iteration, edge-major state in HBM.
+size_t plain_workspace_bytes(const DevCode& c, int64_t B);
+hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, void* ws,
+                        hipStream_t stream);
+
+// Launch shape of the group kernel chosen by the autotuner.
+struct GroupTile {
+  int shots_per_wg = 1;
+  int threads = 256;
+  int grid = 0;          // persistent workgroups
+  size_t lds_bytes = 0;  // dynamic LDS per workgroup
+  bool info16 = false;   // 16-bit per-check info (row degree <= 12)
+};
+
+// Group decoder (group.hip): persistent fused kernel, one workgroup per shot,
+// the shot's state in dynamic LDS; also the multi-code launch.
+size_t group_lds_bytes_nm(int n, int m, bool posterior, bool info16);
+int group_occupancy(int threads, size_t lds, bool info16, int max_lds);
+hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
+                        const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
+                        const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
+                        int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
+                        size_t lds, bool info16, unsigned long long* queue, hipStream_t stream);
+hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,
+                       unsigned* hist, unsigned* base, int32_t* order, hipStream_t stream);
+
+// Mirror of the device code descriptor used by group.hip.
+struct GCodeHost {
+  int n, m, md;
+  int posterior;
+  const int32_t* h_row_ptr;
+  const int32_t* h_col;
+  const int32_t* h_col_ptr;
+  const int32_t* h_col_edge;
+  const int32_t* h_edge_row;
+  const int32_t* d_row_ptr;
+  const int32_t* d_col;
+  const float* lam;
+};
+
+// Small fill kernel (graph-capture safe replacement for hipMemsetAsync).
+hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream);
+
+}  // namespace bpdc

@@ -1,0 +1,858 @@
+// Host runtime of libbpdc: the C ABI of include/bpdc.h.
+//
+// Responsibilities: validation of codes and parameters, the prior-LLR
+// conversion, device copies of the Tanner graph (CSR + CSC) and of the
+// degeneracy matrix, plans (which kernel family decodes which code, the
+// autotuned tile, the code-specialised lane kernels compiled with hipRTC and
+// cached on disk), workspace sizing, dispatch on the caller's stream, HIP
+// graph capture of the multi-code launch, and the thread-local error state.
+#include "../../include/bpdc.h"
+
+#include <dlfcn.h>
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "lane_spec.h"
+
+// Source of the lane kernel (bpdc_device.h + lane_kernel.hip), generated at build time.
+#include "lane_kernel_src.inc"
+
+namespace {
+
+thread_local std::string g_err;
+
+bpdc_status fail(bpdc_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(BPDC_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool csr_ok(const bpdc_csr* A, std::string* why) {
+  if (!A || !A->row_ptr || (A->row_ptr[A->rows] > 0 && !A->col_idx)) {
+    *why = "null CSR pointer";
+    return false;
+  }
+  if (A->rows < 0 || A->cols < 0) {
+    *why = "negative CSR shape";
+    return false;
+  }
+  if (A->row_ptr[0] != 0) {
+    *why = "row_ptr[0] != 0";
+    return false;
+  }
+  for (int r = 0; r < A->rows; ++r) {
+    if (A->row_ptr[r + 1] < A->row_ptr[r]) {
+      *why = "row_ptr not non-decreasing";
+      return false;
+    }
+    for (int k = A->row_ptr[r]; k < A->row_ptr[r + 1]; ++k) {
+      const int c = A->col_idx[k];
+      if (c < 0 || c >= A->cols) {
+        *why = "column index out of range";
+        return false;
+      }
+      if (k > A->row_ptr[r] && c <= A->col_idx[k - 1]) {
+        *why = "column indices not sorted and unique within a row";
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  const size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+std::string lib_dir() {
+  Dl_info info;
+  if (dladdr((void*)&bpdc_version, &info) && info.dli_fname) {
+    std::string p = info.dli_fname;
+    const size_t k = p.rfind('/');
+    if (k != std::string::npos) return p.substr(0, k);
+  }
+  return ".";
+}
+
+std::string cache_dir() {
+  const char* env = getenv("BPDC_CACHE_DIR");
+  std::string d = env && *env ? std::string(env) : lib_dir() + "/kcache";
+  mkdir(d.c_str(), 0755);
+  return d;
+}
+
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+  for (unsigned char ch : s) {
+    h ^= ch;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+const char* kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+const int kNumRtcOpts = sizeof(kRtcOpts) / sizeof(kRtcOpts[0]);
+
+// Compile (or load from the disk cache) the lane kernel for one code.
+bpdc_status lane_code_object(const std::string& spec, std::vector<char>* image, std::string* path_out) {
+  std::string opts;
+  for (int i = 0; i < kNumRtcOpts; ++i) opts += std::string(kRtcOpts[i]) + " ";
+  const std::string full = "using u32 = unsigned int;\n" + std::string(kLaneDeviceSrc) + "\n" + spec + "\n" +
+                           std::string(kLaneKernelSrc);
+  char key[32];
+  snprintf(key, sizeof(key), "%016llx", (unsigned long long)fnv1a(opts + full));
+  const std::string path = cache_dir() + "/lane_" + key + ".co";
+  if (path_out) *path_out = path;
+  {
+    std::ifstream f(path, std::ios::binary);
+    if (f) {
+      image->assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+      if (!image->empty()) return BPDC_OK;
+    }
+  }
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, full.c_str(), "bpdc_lane.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return fail(BPDC_ERR_HIP, "hiprtcCreateProgram failed");
+  const hiprtcResult rc = hiprtcCompileProgram(prog, kNumRtcOpts, kRtcOpts);
+  if (rc != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    return fail(BPDC_ERR_HIP, "hipRTC compile of the lane kernel failed: %s", log.substr(0, 800).c_str());
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  image->resize(cs);
+  hiprtcGetCode(prog, image->data());
+  hiprtcDestroyProgram(&prog);
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    f.write(image->data(), (std::streamsize)image->size());
+  }
+  rename(tmp.c_str(), path.c_str());
+  return BPDC_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// handles
+
+struct bpdc_code_s {
+  bpdc::HostGraph g;
+  std::vector<float> lam;
+  bpdc::DevCode dev;
+  int device = 0;
+};
+
+struct LaneKernel {
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  int grid = 0;
+  std::string cache_path;
+};
+
+struct CodePlan {
+  int kernel = BPDC_KERNEL_PLAIN;
+  LaneKernel lane;
+  bpdc::GroupTile tile;
+};
+
+struct bpdc_plan_s {
+  std::vector<bpdc_code> codes;
+  bpdc_params params;
+  bpdc::KParams kp;
+  std::vector<CodePlan> per_code;
+  int device = 0;
+  int num_cu = 0;
+  int max_lds = 0;
+  // device table of code descriptors (group kernel, multi-code launch)
+  void* d_code_table = nullptr;
+  int32_t* d_code_by_rank = nullptr;  // codes by descending column count
+  bool multi_ok = false;
+  std::string multi_why;
+  bpdc::GroupTile multi_tile;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+// Mirrors LaneArgs in lane_kernel.hip.
+struct LaneArgsHost {
+  const unsigned long long* syn;
+  long long B;
+  long long shot_offset;
+  unsigned long long* corr;
+  unsigned char* flags;
+  float* post;
+  unsigned long long* cut;
+  short* iters;
+  const float* lam;
+  const int* d_row_ptr;
+  const int* d_col;
+  unsigned long long* queue;
+  float alpha;
+  float lsat;
+  float tie_eps;
+  int T1;
+  int T2;
+  int stop;
+  int tie_lowest;
+  int pad_;
+  unsigned long long seed;
+};
+
+bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) {
+  std::string why;
+  if (!bpdc::lane_eligible(c->g, posterior, &why))
+    return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
+  std::vector<char> image;
+  bpdc_status st = lane_code_object(bpdc::lane_spec(c->g, posterior), &image, &lk->cache_path);
+  if (st != BPDC_OK) return st;
+  HIP_TRY(hipModuleLoadData(&lk->mod, image.data()));
+  HIP_TRY(hipModuleGetFunction(&lk->fn, lk->mod, "bpdc_lane_kernel"));
+  int nb = 0;
+  HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lk->fn, 64, 0));
+  if (nb < 1) return fail(BPDC_ERR_UNSUPPORTED, "lane kernel does not fit on a compute unit");
+  lk->grid = nb * num_cu;
+  return BPDC_OK;
+}
+
+const size_t kLaneWs = 256;
+
+bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, const bpdc::DecodeIO& io,
+                        void* ws, hipStream_t stream) {
+  unsigned long long* queue = (unsigned long long*)ws;
+  HIP_TRY(bpdc::fill_u64((uint64_t*)queue, 0, 1, stream));
+  LaneArgsHost a;
+  a.syn = (const unsigned long long*)io.syn;
+  a.B = io.B;
+  a.shot_offset = io.shot_offset;
+  a.corr = (unsigned long long*)io.corr;
+  a.flags = io.flags;
+  a.post = io.post;
+  a.cut = (unsigned long long*)io.cut;
+  a.iters = io.iters;
+  a.lam = c->dev.lam;
+  a.d_row_ptr = c->dev.d_row_ptr;
+  a.d_col = c->dev.d_col;
+  a.queue = queue;
+  a.alpha = p->kp.alpha;
+  a.lsat = p->kp.lsat;
+  a.tie_eps = p->kp.tie_eps;
+  a.T1 = p->kp.T1;
+  a.T2 = p->kp.T2;
+  a.stop = p->kp.stop;
+  a.tie_lowest = p->kp.tie_lowest;
+  a.pad_ = 0;
+  a.seed = p->kp.seed;
+  void* args[] = {&a};
+  const int64_t want = (io.B + 63) / 64;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cp.lane.grid, want));
+  HIP_TRY(hipModuleLaunchKernel(cp.lane.fn, grid, 1, 1, 64, 1, 1, 0, stream, args, nullptr));
+  return BPDC_OK;
+}
+
+// ---- group kernel: tile selection ---------------------------------------------------------
+
+bool code_info16(const bpdc::DevCode& d) { return d.max_row_deg <= 12; }
+
+bool group_fits(const bpdc_plan_s* p, const bpdc::DevCode& d, std::string* why) {
+  if (d.max_row_deg > 27) {
+    *why = "row degree above 27";
+    return false;
+  }
+  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, code_info16(d));
+  if (lds > (size_t)p->max_lds) {
+    *why = "per-shot state of " + std::to_string(lds) + " bytes exceeds the LDS of one workgroup";
+    return false;
+  }
+  return true;
+}
+
+// Synthetic shots drawn from the code's own priors (SplitMix64-driven Bernoulli
+// errors, s = H e), used only to time candidate launch shapes.
+std::vector<uint64_t> autotune_syndromes(const bpdc_code_s* c, int S, uint64_t seed) {
+  const int m = c->g.m, n = c->g.n, sw = (m + 63) / 64;
+  std::vector<uint64_t> syn((size_t)S * sw, 0);
+  std::vector<double> p(n);
+  for (int v = 0; v < n; ++v) p[v] = 1.0 / (1.0 + std::exp((double)c->lam[v]));
+  uint64_t x = seed;
+  for (int b = 0; b < S; ++b) {
+    for (int v = 0; v < n; ++v) {
+      x += 0x9E3779B97F4A7C15ull;
+      uint64_t z = x;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      if ((double)(z >> 11) * (1.0 / 9007199254740992.0) < p[v])
+        for (int r : c->g.cols[v]) syn[(size_t)b * sw + (r >> 6)] ^= 1ull << (r & 63);
+    }
+  }
+  return syn;
+}
+
+struct TuneBuffers {
+  uint64_t* syn = nullptr;
+  uint64_t* corr = nullptr;
+  uint8_t* flags = nullptr;
+  unsigned long long* queue = nullptr;
+  ~TuneBuffers() {
+    if (syn) (void)hipFree(syn);
+    if (corr) (void)hipFree(corr);
+    if (flags) (void)hipFree(flags);
+    if (queue) (void)hipFree(queue);
+  }
+};
+
+// Time one decode of the synthetic batch with the given group tile (ms), or a
+// negative value if it cannot run.
+float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, TuneBuffers& tb, int S) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0f;
+  const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
+  float best = -1.0f;
+  for (int rep = 0; rep < 2; ++rep) {
+    (void)hipEventRecord(e0, 0);
+    hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
+                                      nullptr, nullptr, nullptr, S, 0, tile.threads, tile.grid, tile.lds_bytes,
+                                      tile.info16, tb.queue, 0);
+    (void)hipEventRecord(e1, 0);
+    if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      best = -1.0f;
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep == 1) best = ms;  // the first run warms caches and code
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::GroupTile* out,
+                              float* best_ms_out) {
+  const bpdc::DevCode& d = p->codes[code]->dev;
+  bpdc::GroupTile base;
+  base.info16 = code_info16(d);
+  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, base.info16);
+  std::vector<int> cands;
+  for (int t : {64, 128, 256, 512, 1024}) {
+    const int work = std::max(d.n, d.m);
+    if (t > 64 && t / 2 >= work) continue;  // more threads than items
+    cands.push_back(t);
+  }
+  auto make = [&](int threads) {
+    bpdc::GroupTile t = base;
+    t.threads = threads;
+    const int nb = bpdc::group_occupancy(threads, t.lds_bytes, t.info16, p->max_lds);
+    t.grid = std::max(1, nb) * p->num_cu;
+    return t;
+  };
+  if (!autotune) {
+    int th = 64;
+    while (th < 512 && th < std::max(d.m, d.n / 2)) th *= 2;
+    *out = make(th);
+    if (best_ms_out) *best_ms_out = -1.0f;
+    return BPDC_OK;
+  }
+  const int S = (int)std::max<int64_t>(64, std::min<int64_t>(4096, (1 << 21) / std::max(1, d.E)));
+  TuneBuffers tb;
+  const int sw = (d.m + 63) / 64, nw = (d.n + 63) / 64;
+  std::vector<uint64_t> hs = autotune_syndromes(p->codes[code], S, 0x5EED0000ull + (uint64_t)code);
+  HIP_TRY(hipMalloc((void**)&tb.syn, hs.size() * 8));
+  HIP_TRY(hipMemcpy(tb.syn, hs.data(), hs.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc((void**)&tb.corr, (size_t)S * nw * 8));
+  HIP_TRY(hipMalloc((void**)&tb.flags, (size_t)S));
+  HIP_TRY(hipMalloc((void**)&tb.queue, 256));
+  (void)sw;
+  float best = -1.0f;
+  for (int th : cands) {
+    bpdc::GroupTile t = make(th);
+    if (bpdc::group_occupancy(th, t.lds_bytes, t.info16, p->max_lds) < 1) continue;
+    const float ms = time_group(p, code, t, tb, S);
+    if (ms > 0 && (best < 0 || ms < best)) {
+      best = ms;
+      *out = t;
+    }
+  }
+  if (best < 0) return fail(BPDC_ERR_UNSUPPORTED, "no group tile could run code %d", code);
+  if (best_ms_out) *best_ms_out = best;
+  return BPDC_OK;
+}
+
+bpdc_status build_code_table(bpdc_plan_s* p) {
+  std::vector<bpdc::GCodeHost> tab(p->codes.size());
+  std::vector<int32_t> rank(p->codes.size());
+  for (size_t i = 0; i < p->codes.size(); ++i) {
+    const bpdc::DevCode& d = p->codes[i]->dev;
+    tab[i] = {d.n, d.m, d.md, p->kp.second_pass_posterior, d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge,
+              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam};
+    rank[i] = (int32_t)i;
+  }
+  std::stable_sort(rank.begin(), rank.end(),
+                   [&](int a, int b) { return p->codes[a]->dev.n > p->codes[b]->dev.n; });
+  HIP_TRY(hipMalloc(&p->d_code_table, tab.size() * sizeof(bpdc::GCodeHost)));
+  HIP_TRY(hipMemcpy(p->d_code_table, tab.data(), tab.size() * sizeof(bpdc::GCodeHost), hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc((void**)&p->d_code_by_rank, rank.size() * sizeof(int32_t)));
+  HIP_TRY(hipMemcpy(p->d_code_by_rank, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  return BPDC_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t multi_ws_bytes(const bpdc_plan_s* p, int64_t B) {
+  return 256 + 2 * align256(p->codes.size() * 4) + align256((size_t)std::max<int64_t>(B, 1) * 4);
+}
+
+bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* syn, const int64_t* syn_off,
+                          uint64_t* corr, const int64_t* corr_off, uint8_t* flags, int16_t* iters, int64_t B,
+                          int64_t shot_offset, void* ws, hipStream_t s) {
+  char* w = (char*)ws;
+  unsigned long long* queue = (unsigned long long*)w;
+  unsigned* hist = (unsigned*)(w + 256);
+  unsigned* base = (unsigned*)(w + 256 + align256(p->codes.size() * 4));
+  int32_t* order = (int32_t*)(w + 256 + 2 * align256(p->codes.size() * 4));
+  HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, s));
+  HIP_TRY(bpdc::group_launch(p->d_code_table, cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
+                             nullptr, iters, B, shot_offset, p->multi_tile.threads, p->multi_tile.grid,
+                             p->multi_tile.lds_bytes, p->multi_tile.info16, queue, s));
+  return BPDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bpdc_version(void) { return "bpdc 0.1 gfx950 (plain, lane[hipRTC], group)"; }
+
+const char* bpdc_status_string(bpdc_status s) {
+  switch (s) {
+    case BPDC_OK: return "ok";
+    case BPDC_ERR_INVALID_ARG: return "invalid argument";
+    case BPDC_ERR_UNSUPPORTED: return "unsupported";
+    case BPDC_ERR_WORKSPACE: return "workspace too small";
+    case BPDC_ERR_HIP: return "HIP runtime error";
+    case BPDC_ERR_OOM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+const char* bpdc_last_error(void) { return g_err.c_str(); }
+
+bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double* h_priors, bpdc_code* out) {
+  if (!out) return fail(BPDC_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (!H || !D || !h_priors) return fail(BPDC_ERR_INVALID_ARG, "null H, D or priors");
+  std::string why;
+  if (!csr_ok(H, &why)) return fail(BPDC_ERR_INVALID_ARG, "H: %s", why.c_str());
+  if (!csr_ok(D, &why)) return fail(BPDC_ERR_INVALID_ARG, "D: %s", why.c_str());
+  if (D->cols != H->cols) return fail(BPDC_ERR_INVALID_ARG, "D has %d columns, H has %d", D->cols, H->cols);
+  if (H->cols < 1 || H->rows < 1) return fail(BPDC_ERR_INVALID_ARG, "empty H");
+  for (int v = 0; v < H->cols; ++v)
+    if (!(h_priors[v] > 0.0 && h_priors[v] < 1.0))
+      return fail(BPDC_ERR_INVALID_ARG, "prior %d = %g outside (0, 1)", v, h_priors[v]);
+  auto c = std::make_unique<bpdc_code_s>();
+  bpdc::HostGraph& g = c->g;
+  g.n = H->cols;
+  g.m = H->rows;
+  g.rows.resize(g.m);
+  g.cols.resize(g.n);
+  for (int r = 0; r < g.m; ++r)
+    for (int k = H->row_ptr[r]; k < H->row_ptr[r + 1]; ++k) {
+      g.rows[r].push_back(H->col_idx[k]);
+      g.cols[H->col_idx[k]].push_back(r);
+    }
+  g.drows.resize(D->rows);
+  for (int r = 0; r < D->rows; ++r)
+    for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
+  bpdc::DevCode& d = c->dev;
+  d.n = g.n;
+  d.m = g.m;
+  d.md = D->rows;
+  d.E = H->row_ptr[H->rows];
+  d.dnnz = D->row_ptr[D->rows];
+  for (auto& r : g.rows) d.max_row_deg = std::max(d.max_row_deg, (int)r.size());
+  for (auto& r : g.cols) d.max_col_deg = std::max(d.max_col_deg, (int)r.size());
+  for (auto& r : g.drows) d.max_drow_deg = std::max(d.max_drow_deg, (int)r.size());
+  if (d.max_row_deg > 32) return fail(BPDC_ERR_UNSUPPORTED, "H row degree %d above 32", d.max_row_deg);
+  if (d.max_col_deg > 16) return fail(BPDC_ERR_UNSUPPORTED, "H column degree %d above 16", d.max_col_deg);
+  if (d.max_drow_deg > 32) return fail(BPDC_ERR_UNSUPPORTED, "D row degree %d above 32", d.max_drow_deg);
+  // prior LLR: log((1 - p) / p) in double, rounded once to float
+  c->lam.resize(g.n);
+  for (int v = 0; v < g.n; ++v) c->lam[v] = (float)std::log((1.0 - h_priors[v]) / h_priors[v]);
+  // CSR / CSC / D arrays
+  std::vector<int32_t> hrp(H->row_ptr, H->row_ptr + g.m + 1), hci(H->col_idx, H->col_idx + d.E);
+  std::vector<int32_t> cp(g.n + 1, 0), ce, er(d.E);
+  for (int r = 0; r < g.m; ++r)
+    for (int k = hrp[r]; k < hrp[r + 1]; ++k) er[k] = r;
+  {
+    std::vector<std::vector<int32_t>> per(g.n);
+    for (int r = 0; r < g.m; ++r)
+      for (int k = hrp[r]; k < hrp[r + 1]; ++k) per[hci[k]].push_back(k);
+    for (int v = 0; v < g.n; ++v) {
+      cp[v + 1] = cp[v] + (int)per[v].size();
+      ce.insert(ce.end(), per[v].begin(), per[v].end());
+    }
+  }
+  std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
+  if (hipGetDevice(&c->device) != hipSuccess) return fail(BPDC_ERR_HIP, "no HIP device");
+  hipError_t e;
+  if ((e = upload(&d.h_row_ptr, hrp)) != hipSuccess || (e = upload(&d.h_col, hci)) != hipSuccess ||
+      (e = upload(&d.h_col_ptr, cp)) != hipSuccess || (e = upload(&d.h_col_edge, ce)) != hipSuccess ||
+      (e = upload(&d.h_edge_row, er)) != hipSuccess || (e = upload(&d.d_row_ptr, drp)) != hipSuccess ||
+      (e = upload(&d.d_col, dci)) != hipSuccess || (e = upload(&d.lam, c->lam)) != hipSuccess) {
+    bpdc_code_destroy(c.release());
+    return fail(e == hipErrorOutOfMemory ? BPDC_ERR_OOM : BPDC_ERR_HIP, "upload: %s", hipGetErrorString(e));
+  }
+  *out = c.release();
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_code_destroy(bpdc_code c) {
+  if (!c) return BPDC_OK;
+  bpdc::DevCode& d = c->dev;
+  void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row, d.d_row_ptr, d.d_col, d.lam};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_code_info(bpdc_code c, int32_t* n, int32_t* m, int32_t* md, int32_t* edges) {
+  if (!c) return fail(BPDC_ERR_INVALID_ARG, "null code");
+  if (n) *n = c->dev.n;
+  if (m) *m = c->dev.m;
+  if (md) *md = c->dev.md;
+  if (edges) *edges = c->dev.E;
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior) {
+  std::string why;
+  if (!H || !D || !csr_ok(H, &why) || !csr_ok(D, &why) || H->cols != D->cols)
+    return fail(BPDC_ERR_INVALID_ARG, "bad CSR: %s", why.c_str());
+  bpdc::HostGraph g;
+  g.n = H->cols;
+  g.m = H->rows;
+  g.rows.resize(g.m);
+  g.cols.resize(g.n);
+  for (int r = 0; r < g.m; ++r)
+    for (int k = H->row_ptr[r]; k < H->row_ptr[r + 1]; ++k) {
+      g.rows[r].push_back(H->col_idx[k]);
+      g.cols[H->col_idx[k]].push_back(r);
+    }
+  g.drows.resize(D->rows);
+  for (int r = 0; r < D->rows; ++r)
+    for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
+  if (!bpdc::lane_eligible(g, posterior != 0, &why))
+    return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
+  std::vector<char> image;
+  return lane_code_object(bpdc::lane_spec(g, posterior != 0), &image, nullptr);
+}
+
+bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
+                             int32_t kernel, bpdc_plan* out) {
+  if (!out) return fail(BPDC_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (!codes || ncodes < 1 || !params) return fail(BPDC_ERR_INVALID_ARG, "need >= 1 code and params");
+  for (int i = 0; i < ncodes; ++i)
+    if (!codes[i]) return fail(BPDC_ERR_INVALID_ARG, "code %d is null", i);
+  const bpdc_params& P = *params;
+  if (P.max_iter[0] < 1 || P.max_iter[1] < 1 || P.max_iter[0] > 32767 || P.max_iter[1] > 32767)
+    return fail(BPDC_ERR_INVALID_ARG, "max_iter must be in [1, 32767]");
+  if (!(P.llr_sat > 0.0f) || !std::isfinite(P.llr_sat)) return fail(BPDC_ERR_INVALID_ARG, "llr_sat must be finite and > 0");
+  if (!(P.tie_eps >= 0.0f) || !std::isfinite(P.tie_eps)) return fail(BPDC_ERR_INVALID_ARG, "tie_eps must be >= 0");
+  if (!std::isfinite(P.alpha)) return fail(BPDC_ERR_INVALID_ARG, "alpha must be finite");
+  if (P.second_pass_prior != BPDC_PRIOR_CHANNEL && P.second_pass_prior != BPDC_PRIOR_POSTERIOR)
+    return fail(BPDC_ERR_INVALID_ARG, "bad second_pass_prior");
+  if (P.tie_break != BPDC_TIE_HASH && P.tie_break != BPDC_TIE_LOWEST_INDEX)
+    return fail(BPDC_ERR_INVALID_ARG, "bad tie_break");
+  if (kernel < BPDC_KERNEL_AUTO || kernel > BPDC_KERNEL_GROUP) return fail(BPDC_ERR_INVALID_ARG, "bad kernel");
+  auto p = std::make_unique<bpdc_plan_s>();
+  p->codes.assign(codes, codes + ncodes);
+  p->params = P;
+  p->kp.T1 = P.max_iter[0];
+  p->kp.T2 = P.max_iter[1];
+  p->kp.alpha = P.alpha;
+  p->kp.lsat = P.llr_sat;
+  p->kp.tie_eps = P.tie_eps;
+  p->kp.second_pass_posterior = P.second_pass_prior == BPDC_PRIOR_POSTERIOR;
+  p->kp.stop = P.stop_on_converge != 0;
+  p->kp.tie_lowest = P.tie_break == BPDC_TIE_LOWEST_INDEX;
+  p->kp.seed = P.seed;
+  HIP_TRY(hipGetDevice(&p->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, p->device));
+  p->num_cu = prop.multiProcessorCount;
+  {
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, p->device) != hipSuccess)
+      optin = 0;
+    p->max_lds = std::max<int>((int)prop.sharedMemPerBlock, optin);
+  }
+  p->per_code.resize(ncodes);
+  bpdc_status st = build_code_table(p.get());
+  if (st != BPDC_OK) return st;
+  const bool posterior = p->kp.second_pass_posterior != 0;
+  for (int i = 0; i < ncodes; ++i) {
+    CodePlan& cp = p->per_code[i];
+    bpdc_code c = codes[i];
+    if (kernel == BPDC_KERNEL_PLAIN) {
+      cp.kernel = BPDC_KERNEL_PLAIN;
+      continue;
+    }
+    std::string why_lane, why_group;
+    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, &why_lane);
+    const bool group_ok = group_fits(p.get(), c->dev, &why_group);
+    if (kernel == BPDC_KERNEL_LANE) {
+      if ((st = build_lane(c, posterior, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      cp.kernel = BPDC_KERNEL_LANE;
+      continue;
+    }
+    if (kernel == BPDC_KERNEL_GROUP) {
+      if (!group_ok) return fail(BPDC_ERR_UNSUPPORTED, "group kernel cannot run code %d: %s", i, why_group.c_str());
+      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
+      cp.kernel = BPDC_KERNEL_GROUP;
+      continue;
+    }
+    // AUTO: the code-specialised lane kernel when the code fits one lane,
+    // otherwise the autotuned group kernel
+    if (lane_ok) {
+      if ((st = build_lane(c, posterior, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      cp.kernel = BPDC_KERNEL_LANE;
+    } else if (group_ok) {
+      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
+      cp.kernel = BPDC_KERNEL_GROUP;
+    } else {
+      return fail(BPDC_ERR_UNSUPPORTED, "no fused kernel for code %d (lane: %s; group: %s)", i, why_lane.c_str(),
+                  why_group.c_str());
+    }
+  }
+  // multi-code launch: the group kernel over all codes, LDS sized for the largest
+  p->multi_ok = true;
+  {
+    bool all16 = true;
+    size_t lds = 0;
+    int maxw = 0;
+    for (int i = 0; i < ncodes; ++i) {
+      std::string why;
+      if (!group_fits(p.get(), codes[i]->dev, &why)) {
+        p->multi_ok = false;
+        p->multi_why = "code " + std::to_string(i) + ": " + why;
+      }
+      all16 = all16 && code_info16(codes[i]->dev);
+      maxw = std::max(maxw, std::max(codes[i]->dev.n, codes[i]->dev.m));
+    }
+    for (int i = 0; i < ncodes; ++i)
+      lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, posterior, all16));
+    if (lds > (size_t)p->max_lds) {
+      p->multi_ok = false;
+      p->multi_why = "largest per-shot state exceeds the LDS of one workgroup";
+    }
+    if (p->multi_ok) {
+      bpdc::GroupTile t;
+      t.info16 = all16;
+      t.lds_bytes = lds;
+      int th = 64;
+      while (th < 512 && th < maxw / 2) th *= 2;
+      // autotuned tile of the largest code, when one was chosen
+      int big = 0;
+      for (int i = 1; i < ncodes; ++i)
+        if (codes[i]->dev.n > codes[big]->dev.n) big = i;
+      if (p->per_code[big].kernel == BPDC_KERNEL_GROUP) th = p->per_code[big].tile.threads;
+      t.threads = th;
+      const int nb = bpdc::group_occupancy(th, lds, all16, p->max_lds);
+      t.grid = std::max(1, nb) * p->num_cu;
+      p->multi_tile = t;
+    }
+  }
+  *out = p.release();
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_plan_destroy(bpdc_plan p) {
+  if (!p) return BPDC_OK;
+  for (auto& cp : p->per_code)
+    if (cp.lane.mod) (void)hipModuleUnload(cp.lane.mod);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_code_table) (void)hipFree(p->d_code_table);
+  if (p->d_code_by_rank) (void)hipFree(p->d_code_by_rank);
+  delete p;
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_plan_info(bpdc_plan p, int32_t code, int32_t* kernel, int32_t* shots_per_wg,
+                           int32_t* threads_per_wg) {
+  if (!p || code < 0 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad plan/code");
+  const CodePlan& cp = p->per_code[code];
+  if (kernel) *kernel = cp.kernel;
+  if (shots_per_wg) *shots_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 : (cp.kernel == BPDC_KERNEL_GROUP ? 1 : 0);
+  if (threads_per_wg) *threads_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 : (cp.kernel == BPDC_KERNEL_GROUP ? cp.tile.threads : 256);
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_workspace_size(bpdc_plan p, int32_t code, int64_t B, size_t* bytes) {
+  if (!p || !bytes || B < 0) return fail(BPDC_ERR_INVALID_ARG, "bad arguments");
+  if (code == -1) {
+    *bytes = multi_ws_bytes(p, B);
+    return BPDC_OK;
+  }
+  if (code < 0 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad code index");
+  const CodePlan& cp = p->per_code[code];
+  switch (cp.kernel) {
+    case BPDC_KERNEL_PLAIN: *bytes = bpdc::plain_workspace_bytes(p->codes[code]->dev, B); break;
+    default: *bytes = kLaneWs; break;
+  }
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_t B, int64_t shot_offset,
+                        uint64_t* d_corr, uint8_t* d_flags, float* d_post, uint64_t* d_cut, int16_t* d_iters,
+                        void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (code < 0 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad code index");
+  if (B < 0 || shot_offset < 0) return fail(BPDC_ERR_INVALID_ARG, "negative batch or offset");
+  if (B == 0) return BPDC_OK;
+  if (!d_syn || !d_corr || !d_flags) return fail(BPDC_ERR_INVALID_ARG, "null syndrome/correction/flags");
+  size_t need = 0;
+  bpdc_status st = bpdc_workspace_size(p, code, B, &need);
+  if (st != BPDC_OK) return st;
+  if (!d_ws || ws_bytes < need) return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(BPDC_ERR_INVALID_ARG, "plan was created on device %d, current is %d", p->device, dev);
+  const CodePlan& cp = p->per_code[code];
+  bpdc_code c = p->codes[code];
+  bpdc::DecodeIO io{d_syn, B, shot_offset, d_corr, d_flags, d_post, d_cut, d_iters};
+  hipStream_t s = (hipStream_t)stream;
+  switch (cp.kernel) {
+    case BPDC_KERNEL_PLAIN:
+      HIP_TRY(bpdc::plain_decode(c->dev, p->kp, io, d_ws, s));
+      return BPDC_OK;
+    case BPDC_KERNEL_LANE:
+      return lane_launch(p, cp, c, io, d_ws, s);
+    case BPDC_KERNEL_GROUP: {
+      const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
+      HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
+                                 d_cut, d_iters, B, shot_offset, cp.tile.threads, cp.tile.grid, cp.tile.lds_bytes,
+                                 cp.tile.info16, (unsigned long long*)d_ws, s));
+      return BPDC_OK;
+    }
+    default:
+      return fail(BPDC_ERR_UNSUPPORTED, "kernel family not available");
+  }
+}
+
+bpdc_status bpdc_decode_multi(bpdc_plan p, const int32_t* d_code_of_shot, const uint64_t* d_syn,
+                              const int64_t* d_syn_off, uint64_t* d_corr, const int64_t* d_corr_off,
+                              uint8_t* d_flags, int16_t* d_iters, int64_t B, int64_t shot_offset, void* d_ws,
+                              size_t ws_bytes, void* stream) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (B < 0 || shot_offset < 0) return fail(BPDC_ERR_INVALID_ARG, "negative batch or offset");
+  if (B == 0) return BPDC_OK;
+  if (B > 0x7fffffff) return fail(BPDC_ERR_INVALID_ARG, "multi-code batch above 2^31 shots");
+  if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
+    return fail(BPDC_ERR_INVALID_ARG, "null pointer");
+  if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
+  if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
+    return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
+  return multi_enqueue(p, d_code_of_shot, d_syn, d_syn_off, d_corr, d_corr_off, d_flags, d_iters, B, shot_offset,
+                       d_ws, (hipStream_t)stream);
+}
+
+bpdc_status bpdc_graph_capture_multi(bpdc_plan p, const int32_t* d_code_of_shot, const uint64_t* d_syn,
+                                     const int64_t* d_syn_off, uint64_t* d_corr, const int64_t* d_corr_off,
+                                     uint8_t* d_flags, int16_t* d_iters, int64_t B, int64_t shot_offset,
+                                     void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (B <= 0 || shot_offset < 0 || B > 0x7fffffff) return fail(BPDC_ERR_INVALID_ARG, "bad batch size");
+  if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
+    return fail(BPDC_ERR_INVALID_ARG, "null pointer");
+  if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
+  if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
+    return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
+  hipStream_t s = (hipStream_t)stream;
+  hipStream_t cs = s;
+  bool own = false;
+  if (!cs) {  // the null stream cannot be captured: capture on a private stream
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    own = true;
+  }
+  if (p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  bpdc_status st = BPDC_OK;
+  if (e == hipSuccess) {
+    st = multi_enqueue(p, d_code_of_shot, d_syn, d_syn_off, d_corr, d_corr_off, d_flags, d_iters, B, shot_offset,
+                       d_ws, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (st == BPDC_OK && e2 != hipSuccess) st = fail(BPDC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    if (st == BPDC_OK) {
+      p->graph = g;
+      const hipError_t e3 = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+      if (e3 != hipSuccess) st = fail(BPDC_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  } else {
+    st = fail(BPDC_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  if (own) (void)hipStreamDestroy(cs);
+  return st;
+}
+
+bpdc_status bpdc_graph_launch(bpdc_plan p, void* stream) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (!p->graph_exec) return fail(BPDC_ERR_INVALID_ARG, "no graph captured on this plan");
+  HIP_TRY(hipGraphLaunch(p->graph_exec, (hipStream_t)stream));
+  return BPDC_OK;
+}
+
+}  // extern "C"
