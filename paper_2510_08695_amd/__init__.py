@@ -6,10 +6,10 @@ arguments, with torch tensors supplying device memory and the current stream.
 Importing it does not load the library; the first use does, and raises if
 the library has not been built.
 """
-from ._lib import (BpdcError, Params, Code, Plan, lib, lib_path, lane_precompile,
+from ._lib import (BpdcError, Params, Code, Plan, lib, lib_path, lane_precompile, weighted_bpdc,
                    KERNEL_AUTO, KERNEL_PLAIN, KERNEL_LANE, KERNEL_GROUP,
                    PRIOR_CHANNEL, PRIOR_POSTERIOR, TIE_HASH, TIE_LOWEST_INDEX)
 
-__all__ = ["BpdcError", "Params", "Code", "Plan", "lib", "lib_path", "lane_precompile",
+__all__ = ["BpdcError", "Params", "Code", "Plan", "lib", "lib_path", "lane_precompile", "weighted_bpdc",
            "KERNEL_AUTO", "KERNEL_PLAIN", "KERNEL_LANE", "KERNEL_GROUP",
            "PRIOR_CHANNEL", "PRIOR_POSTERIOR", "TIE_HASH", "TIE_LOWEST_INDEX"]

@@ -236,6 +236,84 @@ class Plan:
                                  _ptr(out.get("iters")), _ptr(ws), ws.numel(), _stream()))
         return out
 
+    # ---- multi-code batch -------------------------------------------------------------
+    def multi_buffers(self, code_of_shot, B=None):
+        """Offsets for a mixed batch: returns (syn_off, corr_off, syn_words, corr_words) as int64
+        tensors/ints, packing each shot's words consecutively in batch order."""
+        import torch
+        cos = code_of_shot.cpu().numpy().astype(np.int64)
+        sw = np.array([(c.m + 63) // 64 for c in self.codes], np.int64)[cos]
+        nw = np.array([(c.n + 63) // 64 for c in self.codes], np.int64)[cos]
+        syn_off = np.concatenate([[0], np.cumsum(sw)[:-1]]) if len(cos) else np.zeros(0, np.int64)
+        corr_off = np.concatenate([[0], np.cumsum(nw)[:-1]]) if len(cos) else np.zeros(0, np.int64)
+        return (torch.from_numpy(syn_off).cuda(), torch.from_numpy(corr_off).cuda(),
+                int(sw.sum()), int(nw.sum()))
+
+    def multi_workspace(self, B: int):
+        import torch
+        n = C.c_size_t()
+        _check(lib().bpdc_workspace_size(self.handle, -1, B, C.byref(n)))
+        ws = self._ws.get(-1)
+        if ws is None or ws.numel() < n.value:
+            ws = torch.empty(max(256, n.value), dtype=torch.uint8, device="cuda")
+            self._ws[-1] = ws
+        return ws
+
+    def decode_multi(self, code_of_shot, syn, syn_off, corr, corr_off, flags, iters=None,
+                     shot_offset: int = 0):
+        """One persistent launch over a mixed batch (all tensors on the GPU)."""
+        B = code_of_shot.shape[0]
+        ws = self.multi_workspace(B)
+        _check(lib().bpdc_decode_multi(self.handle, _ptr(code_of_shot), _ptr(syn), _ptr(syn_off), _ptr(corr),
+                                       _ptr(corr_off), _ptr(flags), _ptr(iters), B, shot_offset, _ptr(ws),
+                                       ws.numel(), _stream()))
+
+    def capture_multi(self, code_of_shot, syn, syn_off, corr, corr_off, flags, iters=None,
+                      shot_offset: int = 0):
+        """Capture decode_multi on these buffers into a HIP graph held by the plan."""
+        B = code_of_shot.shape[0]
+        ws = self.multi_workspace(B)
+        self._graph_keep = (code_of_shot, syn, syn_off, corr, corr_off, flags, iters, ws)
+        _check(lib().bpdc_graph_capture_multi(self.handle, _ptr(code_of_shot), _ptr(syn), _ptr(syn_off),
+                                              _ptr(corr), _ptr(corr_off), _ptr(flags), _ptr(iters), B,
+                                              shot_offset, _ptr(ws), ws.numel(), _stream()))
+
+    def graph_launch(self):
+        _check(lib().bpdc_graph_launch(self.handle, _stream()))
+
+    # ---- weighted min-sum ----------------------------------------------------------------
+    def wms_ckpt_size(self, code: int, B: int, ckpt_every: int) -> int:
+        n = C.c_size_t()
+        _check(lib().bpdc_wms_ckpt_size(self.handle, code, B, ckpt_every, C.byref(n)))
+        return n.value
+
+    def wms_forward(self, w, syn, code: int = 0, shot_offset: int = 0, ckpt_every: int = 5):
+        """Weighted forward: returns dict(post [2,B,n], cut [B,nw], flags [B], ckpt)."""
+        import torch
+        c = self.codes[code]
+        B = syn.shape[0]
+        nw = (c.n + 63) // 64
+        post = torch.empty((2, B, c.n), dtype=torch.float32, device="cuda")
+        cut = torch.empty((B, nw), dtype=torch.int64, device="cuda")
+        flags = torch.empty(B, dtype=torch.uint8, device="cuda")
+        ck = torch.empty(max(4, self.wms_ckpt_size(code, B, ckpt_every)), dtype=torch.uint8, device="cuda")
+        assert w.dtype == torch.float32 and w.is_contiguous() and w.numel() == 2 * c.edges
+        _check(lib().bpdc_wms_forward(self.handle, code, _ptr(w), _ptr(syn), B, shot_offset, ckpt_every,
+                                      _ptr(post), _ptr(cut), _ptr(flags), _ptr(ck), ck.numel(), _stream()))
+        return {"post": post, "cut": cut, "flags": flags, "ckpt": ck, "ckpt_every": ckpt_every}
+
+    def wms_backward(self, w, syn, fwd: dict, grad_post, code: int = 0):
+        """Adjoint of wms_forward: dLoss/dw [2, E] for dLoss/dpost [2, B, n]."""
+        import torch
+        c = self.codes[code]
+        B = syn.shape[0]
+        gw = torch.zeros(2 * c.edges, dtype=torch.float32, device="cuda")
+        gp = grad_post.contiguous().float()
+        _check(lib().bpdc_wms_backward(self.handle, code, _ptr(w), _ptr(syn), B, fwd["ckpt_every"], _ptr(gp),
+                                       _ptr(fwd["cut"]), _ptr(fwd["flags"]), _ptr(fwd["ckpt"]),
+                                       fwd["ckpt"].numel(), _ptr(gw), _stream()))
+        return gw
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().bpdc_plan_destroy(self.handle)
@@ -246,3 +324,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def weighted_bpdc(plan: "Plan", code: int = 0, ckpt_every: int = 5):
+    """torch.autograd.Function over the weighted min-sum BP+DC decoder.
+
+    Returns a callable f(w, syn) -> (post [2, B, n], cut, flags): w is the
+    [2 * E] float32 weight tensor (pass 1, pass 2), syn the packed syndromes.
+    The backward runs the library's adjoint kernel with the cut held fixed.
+    """
+    import torch
+
+    class _WeightedBPDC(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, w, syn):
+            out = plan.wms_forward(w.detach().contiguous(), syn, code=code, ckpt_every=ckpt_every)
+            ctx.save_for_backward(w, syn)
+            ctx.fwd = out
+            ctx.mark_non_differentiable(out["cut"], out["flags"])
+            return out["post"], out["cut"], out["flags"]
+
+        @staticmethod
+        def backward(ctx, g_post, g_cut, g_flags):
+            w, syn = ctx.saved_tensors
+            if g_post is None:
+                return None, None
+            gw = plan.wms_backward(w.detach().contiguous(), syn, ctx.fwd, g_post, code=code)
+            return gw, None
+
+    return _WeightedBPDC.apply

@@ -300,6 +300,7 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
   a.shot_offset = shot_offset;
   a.queue = queue;
   a.p = p;
+  (void)hipGetLastError();  // report only this launch's errors
   hipError_t e = fill_u64((uint64_t*)queue, 0, 1, stream);
   if (e != hipSuccess) return e;
   if (info16) hipLaunchKernelGGL(k_group<uint16_t>, dim3(grid), dim3(threads), lds, stream, a);
@@ -311,11 +312,25 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
 // process and device), then report how many workgroups of `threads` threads
 // and `lds` bytes fit on a compute unit.
 int group_occupancy(int threads, size_t lds, bool info16, int max_lds) {
-  hipFuncSetAttribute((const void*)k_group<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-  hipFuncSetAttribute((const void*)k_group<u32>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  // raise the dynamic-LDS limit of both instantiations once; a refusal leaves
+  // the default limit (and its error is cleared so that it is not reported
+  // by a later launch check)
+  static int raised_to = -1;
+  if (raised_to != max_lds) {
+    if (hipFuncSetAttribute((const void*)k_group<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_group<u32>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+            hipSuccess)
+      (void)hipGetLastError();
+    raised_to = max_lds;
+  }
   int nb = 0;
-  if (info16) hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds);
-  else hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds);
+  hipError_t e = info16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
   return nb;
 }
 

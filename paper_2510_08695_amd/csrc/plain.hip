@@ -222,6 +222,7 @@ hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, 
                         hipStream_t stream) {
   const int64_t B = io.B;
   if (B == 0) return hipSuccess;
+  (void)hipGetLastError();  // report only this decode's errors
   PlainWs w = carve(c, B, ws);
   const int sw64 = (c.m + 63) >> 6;
   const dim3 blk(256);

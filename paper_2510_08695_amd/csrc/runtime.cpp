@@ -135,6 +135,10 @@ bpdc_status lane_code_object(const std::string& spec, std::vector<char>* image, 
   char key[32];
   snprintf(key, sizeof(key), "%016llx", (unsigned long long)fnv1a(opts + full));
   const std::string path = cache_dir() + "/lane_" + key + ".co";
+  if (const char* dump = getenv("BPDC_DUMP_LANE_SOURCE")) {  // for inspecting the generated kernel
+    std::ofstream f(std::string(dump) + "/lane_" + key + ".hip");
+    f << full;
+  }
   if (path_out) *path_out = path;
   {
     std::ifstream f(path, std::ios::binary);
@@ -260,6 +264,7 @@ const size_t kLaneWs = 256;
 bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, const bpdc::DecodeIO& io,
                         void* ws, hipStream_t stream) {
   unsigned long long* queue = (unsigned long long*)ws;
+  (void)hipGetLastError();
   HIP_TRY(bpdc::fill_u64((uint64_t*)queue, 0, 1, stream));
   LaneArgsHost a;
   a.syn = (const unsigned long long*)io.syn;
@@ -414,7 +419,9 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
       *out = t;
     }
   }
-  if (best < 0) return fail(BPDC_ERR_UNSUPPORTED, "no group tile could run code %d", code);
+  if (best < 0)
+    return fail(BPDC_ERR_UNSUPPORTED, "no group tile could run code %d (lds %zu of %d bytes, last HIP error: %s)",
+                code, base.lds_bytes, p->max_lds, hipGetErrorString(hipGetLastError()));
   if (best_ms_out) *best_ms_out = best;
   return BPDC_OK;
 }
@@ -855,4 +862,66 @@ bpdc_status bpdc_graph_launch(bpdc_plan p, void* stream) {
   return BPDC_OK;
 }
 
+// ---- weighted min-sum -------------------------------------------------------------------------
+
+static bpdc_status wms_check(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (code < 0 || code >= (int)p->codes.size()) return fail(BPDC_ERR_INVALID_ARG, "bad code index");
+  if (B < 0) return fail(BPDC_ERR_INVALID_ARG, "negative batch");
+  if (K < 1) return fail(BPDC_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+  if (p->kp.second_pass_posterior)
+    return fail(BPDC_ERR_UNSUPPORTED, "weighted min-sum supports the channel second-pass prior only");
+  const bpdc::DevCode& d = p->codes[code]->dev;
+  if (bpdc::wms_backward_lds(d, K) > (size_t)p->max_lds || bpdc::wms_forward_lds(d) > (size_t)p->max_lds)
+    return fail(BPDC_ERR_UNSUPPORTED, "code too large for the weighted min-sum kernels (LDS)");
+  return BPDC_OK;
+}
+
+static size_t wms_ckpt_bytes(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
+  const bpdc::DevCode& d = p->codes[code]->dev;
+  const int64_t nck = (p->kp.T1 + K - 1) / K + (p->kp.T2 + K - 1) / K;
+  return (size_t)B * (size_t)nck * (size_t)d.E * sizeof(float);
+}
+
+bpdc_status bpdc_wms_ckpt_size(bpdc_plan p, int32_t code, int64_t B, int32_t K, size_t* bytes) {
+  bpdc_status st = wms_check(p, code, B, K);
+  if (st != BPDC_OK) return st;
+  if (!bytes) return fail(BPDC_ERR_INVALID_ARG, "null bytes");
+  *bytes = wms_ckpt_bytes(p, code, B, K);
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_wms_forward(bpdc_plan p, int32_t code, const float* d_w, const uint64_t* d_syn, int64_t B,
+                             int64_t shot_offset, int32_t K, float* d_post, uint64_t* d_cut, uint8_t* d_flags,
+                             void* d_ckpt, size_t ckpt_bytes, void* stream) {
+  bpdc_status st = wms_check(p, code, B, K);
+  if (st != BPDC_OK) return st;
+  if (B == 0) return BPDC_OK;
+  if (shot_offset < 0) return fail(BPDC_ERR_INVALID_ARG, "negative shot offset");
+  if (!d_w || !d_syn || !d_post || !d_cut || !d_flags) return fail(BPDC_ERR_INVALID_ARG, "null pointer");
+  if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
+    return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
+  const int grid = (int)std::min<int64_t>(B, (int64_t)p->num_cu * 8);
+  HIP_TRY(bpdc::wms_forward(p->codes[code]->dev, p->kp, d_w, d_syn, B, shot_offset, K, d_post, d_cut, d_flags,
+                            (float*)d_ckpt, grid, p->max_lds, (hipStream_t)stream));
+  return BPDC_OK;
+}
+
+bpdc_status bpdc_wms_backward(bpdc_plan p, int32_t code, const float* d_w, const uint64_t* d_syn, int64_t B,
+                              int32_t K, const float* d_grad_post, const uint64_t* d_cut, const uint8_t* d_flags,
+                              const void* d_ckpt, size_t ckpt_bytes, float* d_grad_w, void* stream) {
+  bpdc_status st = wms_check(p, code, B, K);
+  if (st != BPDC_OK) return st;
+  if (B == 0) return BPDC_OK;
+  if (!d_w || !d_syn || !d_grad_post || !d_cut || !d_flags || !d_grad_w)
+    return fail(BPDC_ERR_INVALID_ARG, "null pointer");
+  if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
+    return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
+  const int grid = (int)std::min<int64_t>(B, (int64_t)p->num_cu * 4);
+  HIP_TRY(bpdc::wms_backward(p->codes[code]->dev, p->kp, d_w, d_syn, B, K, d_grad_post, d_cut, d_flags,
+                             (const float*)d_ckpt, d_grad_w, grid, p->max_lds, (hipStream_t)stream));
+  return BPDC_OK;
+}
+
 }  // extern "C"
+

@@ -1,0 +1,157 @@
+"""Weighted min-sum BP+DC (learned per-edge scales): forward parity with the
+float32 oracle, reduction to plain scaled min-sum, and the adjoint kernel
+against central finite differences of the float64 oracle (GPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import oracle_params
+
+pytestmark = pytest.mark.gpu
+
+T = (25, 25)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_08695_amd as P
+    code = synth.bb_code("bb144", p=0.05)
+    prm = P.Params(max_iter=T, alpha=0.625, stop_on_converge=False, seed=21)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    return P, code, prm, plan
+
+
+def _run_fwd(plan, code, syndromes, w):
+    import torch
+    syn = torch.from_numpy(synth.pack_bits(syndromes).view(np.int64)).cuda()
+    wt = torch.from_numpy(w.astype(np.float32)).cuda()
+    out = plan.wms_forward(wt, syn, ckpt_every=5)
+    torch.cuda.synchronize()
+    return syn, wt, out
+
+
+@pytest.mark.parametrize("kind", ["uniform", "random"])
+def test_weighted_forward_bit_exact_vs_float32_oracle(setup, kind):
+    P, code, prm, plan = setup
+    shots = synth.make_shots(code, 300, 5001)
+    E = code.H.nnz
+    rng = np.random.default_rng(1)
+    w = np.full(2 * E, 0.625) if kind == "uniform" else 0.625 + 0.1 * rng.standard_normal(2 * E)
+    w = w.astype(np.float32)
+    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w)
+    ref = oracle.decode(code, shots.syndromes, oracle_params(prm, "channel"), precision="f32",
+                        weights=w.astype(np.float64), want_post1=True)
+    post = out["post"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    cut = synth.unpack_bits(out["cut"].cpu().numpy().view(np.uint64), code.n)
+    np.testing.assert_array_equal(flags, ref["flags"])
+    np.testing.assert_array_equal(cut, ref["cut"])
+    np.testing.assert_array_equal(post[0].view(np.uint32), ref["post1"].astype(np.float32).view(np.uint32))
+    dc = (ref["flags"] & 2) != 0
+    assert dc.sum() > 5
+    np.testing.assert_array_equal(post[1][dc].view(np.uint32),
+                                  ref["post"][dc].astype(np.float32).view(np.uint32))
+    if kind == "uniform":
+        # weights all equal to the scale reproduce the unweighted decoder (fixed iterations)
+        plan2 = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
+        from gpu_helpers import gpu_decode
+        g = gpu_decode(plan2, code, shots.syndromes)
+        np.testing.assert_array_equal(g["flags"], flags)
+        np.testing.assert_array_equal(g["cut"], cut)
+
+
+def _loss_and_grad_post(post, errors, cut, flags):
+    """Mean over shots of BCE(pass-1 posteriors, e) + [DC] * BCE(pass-2 posteriors on
+    non-cut columns, e), BCE in LLR form e*softplus(L) + (1-e)*softplus(-L)."""
+    e = errors.astype(np.float64)
+    B, n = e.shape
+    L1, L2 = post[0].astype(np.float64), post[1].astype(np.float64)
+    dc = ((flags & 2) != 0)[:, None]
+    keep2 = dc & (cut == 0)
+    L2 = np.where(keep2, L2, 0.0)
+
+    def bce(L):
+        return e * np.logaddexp(0, L) + (1 - e) * np.logaddexp(0, -L)
+
+    def dbce(L):
+        return 1.0 / (1.0 + np.exp(-L)) - (1 - e)
+
+    loss = (bce(L1).sum() + (bce(L2) * keep2).sum()) / B
+    g = np.stack([dbce(L1) / B, np.where(keep2, dbce(L2), 0.0) / B])
+    return loss, g
+
+
+def test_adjoint_matches_finite_differences_of_float64_oracle(setup):
+    import torch
+    P, code, prm, plan = setup
+    B = 256
+    shots = synth.make_shots(code, B, 5002)
+    E = code.H.nnz
+    rng = np.random.default_rng(2)
+    w = (0.625 + 0.05 * rng.standard_normal(2 * E)).astype(np.float32)
+    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w)
+    post = out["post"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    cut = synth.unpack_bits(out["cut"].cpu().numpy().view(np.uint64), code.n)
+    _, gpost = _loss_and_grad_post(post, shots.errors, cut, flags)
+    gw = plan.wms_backward(wt, syn, out, torch.from_numpy(gpost.astype(np.float32)).cuda()).cpu().numpy()
+    op = oracle_params(prm, "channel")
+
+    def f64_loss(wv):
+        o = oracle.decode(code, shots.syndromes, op, precision="f64", weights=wv, want_post1=True)
+        post64 = np.stack([o["post1"], o["post"]])
+        return _loss_and_grad_post(post64, shots.errors, o["cut"], o["flags"])[0], o["cut"]
+
+    w64 = w.astype(np.float64)
+    base, base_cut = f64_loss(w64)
+    idx = rng.choice(2 * E, size=48, replace=False)
+    checked = 0
+    for j in idx:
+        h = 1e-4 * max(1.0, abs(w64[j]))
+        wp, wm = w64.copy(), w64.copy()
+        wp[j] += h
+        wm[j] -= h
+        lp, cp = f64_loss(wp)
+        lm, cm = f64_loss(wm)
+        if not ((cp == base_cut).all() and (cm == base_cut).all()):
+            continue  # the cut changed: a kink of the piecewise-smooth loss
+        fwd, bwd = (lp - base) / h, (base - lm) / h
+        if abs(fwd - bwd) > 1e-3 * max(1e-3, abs(fwd) + abs(bwd)):
+            continue  # a min / sign switch inside [w - h, w + h]
+        fd = (lp - lm) / (2 * h)
+        assert abs(gw[j] - fd) <= 2e-3 * max(abs(fd), 1e-3), (j, gw[j], fd)
+        checked += 1
+    assert checked >= 24, checked
+    assert np.isfinite(gw).all() and np.abs(gw).max() > 0
+
+
+def test_autograd_function_and_training_step_reduce_loss(setup):
+    import torch
+    P, code, prm, plan = setup
+    f = P.weighted_bpdc(plan, ckpt_every=5)
+    E = code.H.nnz
+    w = torch.full((2 * E,), 0.625, dtype=torch.float32, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([w], lr=1e-2)
+    losses = []
+    for step in range(12):
+        sh = synth.make_shots(code, 512, 7000 + step % 3)
+        syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
+        e = torch.from_numpy(sh.errors.astype(np.float32)).cuda()
+        post, cut, flags = f(w, syn)
+        dc = ((flags & 2) != 0).float()[:, None]
+        cutb = torch.from_numpy(synth.unpack_bits(cut.cpu().numpy().view(np.uint64), code.n)).cuda()
+        keep2 = dc * (1 - cutb.float())
+        L1 = post[0]
+        L2 = torch.where(keep2 > 0, post[1], torch.zeros_like(post[1]))
+        bce = lambda L: e * torch.nn.functional.softplus(L) + (1 - e) * torch.nn.functional.softplus(-L)
+        loss = (bce(L1).sum() + (bce(L2) * keep2).sum()) / e.shape[0]
+        opt.zero_grad()
+        loss.backward()
+        assert w.grad is not None and torch.isfinite(w.grad).all()
+        opt.step()
+        losses.append(loss.item())
+    assert np.mean(losses[-3:]) < np.mean(losses[:3])
