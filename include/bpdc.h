@@ -179,9 +179,11 @@ bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
 /* Compile, or find in the on-disk kernel cache, the code-specialised lane
  * kernel for (H, D) without touching a GPU (host-only; hipRTC).  The cache
  * directory is $BPDC_CACHE_DIR, else kcache/ beside libbpdc.so.  posterior =
- * 1 for plans with BPDC_PRIOR_POSTERIOR.  BPDC_ERR_UNSUPPORTED if the code is
- * too large for the lane kernel. */
-bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior);
+ * 1 for plans with BPDC_PRIOR_POSTERIOR; uniform_prior = 1 for codes whose
+ * priors are all equal (the kernel then takes the prior as one value).
+ * BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
+bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior,
+                                 int32_t uniform_prior);
 
 const char* bpdc_status_string(bpdc_status status);
 const char* bpdc_last_error(void);

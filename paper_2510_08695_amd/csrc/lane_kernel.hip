@@ -1,35 +1,40 @@
-// Fused persistent BP -> DC -> BP kernel, one shot per lane (gfx950, wave64).
+// Fused persistent BP -> DC -> BP kernel, one shot per lane or per pair of
+// lanes (gfx950, wave64).
 //
 // This source is compiled at plan-creation time with hipRTC, after the
 // device helpers (bpdc_device.h) and a generated specification of one code:
-// sizes (NB_*), and NB_SWEEP(), a straight-line sweep over the code's Tanner
-// graph with every index a literal.  Everything a lane needs for its shot
-// therefore lives in registers at fixed places:
+// sizes (NB_*), lookup tables, and NB_SWEEP(), a straight-line sweep over the
+// code's Tanner graph with every index a literal.  Everything a lane needs
+// for its shot therefore lives in registers at fixed places:
 //
-//   per check c : A1[c], A2[c]  alpha * (smallest, second smallest |q|)
-//                 a field of W[] holding, per incident edge, the sign of the
-//                 check-to-variable message r and a one-hot argmin bit;
-//                 r = sign * (edge is argmin ? A2 : A1) (scaled min-sum,
-//                 the check rule of Sec. II.C);
-//   per column  : the cut bit C[], and the posterior L written to LDS
-//                 (sL, [column][65 lanes]) every sweep for DC and output.
+//   per check ("slot") s : A1[s], A2[s] = alpha * (smallest, second smallest
+//                 |q|); a field of W[] holding, per incident edge, the sign of
+//                 the check-to-variable message r and a one-hot argmin bit;
+//                 r = sign * (edge is argmin ? A2 : A1) (scaled min-sum);
+//   per column ("row") i : the cut bit C[], and the posterior L written to
+//                 LDS (sL, [row][65 lanes]) every sweep for DC and output.
 //
-// One sweep visits every column v once: L_v = lambda_v + sum_c r_{c->v}
-// (ascending check order), the hard decision and the stop-test parity of
-// each check (H e = s, Sec. II.C), then q_{v->c} = sat(L_v - r_{c->v}) and
-// its contribution to the next check state of c (min, second min, argmin,
-// sign parity).  A check's new state is completed ("finalised") at its last
-// edge in the sweep, so one sweep is the variable half of iteration t and the
-// check half of iteration t + 1 (flooding schedule).  The very first sweep of
-// a pass starts from an all-zero check state, which makes L = lambda and
-// q = sat(lambda), the first-iteration messages.
+// In the paired layout two adjacent lanes share a shot: lane A holds checks
+// 0..m/2-1 and a set of columns, lane B the images of both under an
+// automorphism of the code, and the edges that cross between the halves are
+// exchanged with DPP lane swaps (see lane_spec.cpp).
 //
-// Lanes are independent shots; a lane whose pass ends (converged, or T
-// iterations) is handled by the whole wave: degeneracy cutting (Sec. III.A,
-// one D row per lane, nominees OR-ed into an LDS bitmask), or output of the
-// packed correction with one ballot per 64 columns; then the lane takes the
-// next shot from a global counter.  The kernel is persistent: a wave exits
-// when the counter is past the batch and all its lanes are idle.
+// One sweep visits every row once: L = lambda + sum of r (ascending check
+// order), the hard decision and the stop-test parity of each check (H e = s,
+// Sec. II.C), then q = sat(L - r) and its contribution to the next check
+// state (min, second min, argmin, sign parity).  A check's new state is
+// completed ("finalised") at its last edge in the sweep, so one sweep is the
+// variable half of iteration t and the check half of iteration t + 1
+// (flooding schedule).  The first sweep of a pass starts from an all-zero
+// check state, which makes L = lambda and q = sat(lambda), the first-iteration
+// messages.
+//
+// A shot whose pass ends (converged, or T iterations) is handled by the whole
+// wave: degeneracy cutting (Sec. III.A, one D row per lane, nominees OR-ed
+// into LDS bitmasks), or output of the packed correction with one ballot per
+// 64 columns; then its lane(s) take the next shot from a global counter.  The
+// kernel is persistent: a wave exits when the counter is past the batch and
+// all its lanes are idle.
 
 struct LaneArgs {
   const unsigned long long* syn;  // [B][NB_SW64]
@@ -47,15 +52,15 @@ struct LaneArgs {
   float alpha;
   float lsat;
   float tie_eps;
+  float lam_uniform;              // the prior LLR when all priors are equal
   int T1;
   int T2;
   int stop;
   int tie_lowest;
-  int pad_;
   unsigned long long seed;
 };
 
-#define NB_STRIDE 65  // LDS row stride (floats) of the [column][lane] posterior array
+#define NB_STRIDE 65  // LDS row stride (floats) of the [row][lane] posterior array
 
 namespace bpdc_lane {
 using bpdc_dev::u32;
@@ -79,8 +84,7 @@ __device__ __forceinline__ u32 bfi(u32 mask, u32 a, u32 b) {
 // r for the edge slot whose one-hot argmin bit is `op` and whose sign bit is
 // `sp` in the check field word w: magnitude A2 if the edge holds the
 // minimum, else A1; sign from the field.
-__device__ __forceinline__ float dec(float a1, float a2, u32 w, const int op, const int sp,
-                                     u32 signmask) {
+__device__ __forceinline__ float dec(float a1, float a2, u32 w, const int op, const int sp, u32 signmask) {
   const u32 mask = (u32)__builtin_amdgcn_sbfe((int)w, op, 1);
   const u32 mag = bfi(mask, __float_as_uint(a2), __float_as_uint(a1));
   return __uint_as_float(bfi(signmask, w << (31 - sp), mag));
@@ -92,88 +96,120 @@ __device__ __forceinline__ float cutsel(float L, u32 cw, const int b, u32 infbit
   const u32 mask = (u32)__builtin_amdgcn_sbfe((int)cw, b, 1);
   return __uint_as_float(bfi(mask, infbits, __float_as_uint(L)));
 }
+
+// Exchange with the adjacent lane (lanes 2i <-> 2i+1): one DPP move.
+__device__ __forceinline__ u32 swapu(u32 x) {
+  return (u32)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float swapf(float x) { return __uint_as_float(swapu(__float_as_uint(x))); }
+
+// Bits [start, start + 32) of the little-endian bit vector S (zero beyond).
+template <int NW>
+__device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
+  const int w = start >> 5, sh = start & 31;
+  const u32 lo = (w < NW) ? S[(w < NW) ? w : 0] : 0u;
+  const u32 hi = (w + 1 < NW) ? S[(w + 1 < NW) ? w + 1 : 0] : 0u;
+  return sh ? __builtin_amdgcn_alignbit(hi, lo, sh) : lo;
+}
 }  // namespace bpdc_lane
 
-// Accumulate q into the next state of check c (slot bit b): first slot / later slots.
-#define NB_ACC0(c, q, ev, b)                                   \
+// Accumulate q into the next state of slot s (bit b): first event / later events.
+#define NB_ACC0(s, q, ev, b)                                   \
   {                                                            \
     const float a_ = fabsf(q);                                 \
-    m1_##c = bpdc_lane::absmin(q, LS);                         \
-    m2_##c = LS;                                               \
-    am_##c = (a_ < LS) ? (1u << (b)) : 0u;                     \
-    sb_##c = __float_as_uint(q) >> 31;                         \
-    ep_##c = (ev);                                             \
+    m1_##s = bpdc_lane::absmin(q, LS);                         \
+    m2_##s = LS;                                               \
+    am_##s = (a_ < LS) ? (1u << (b)) : 0u;                     \
+    sb_##s = __float_as_uint(q) >> 31;                         \
+    ep_##s = (ev);                                             \
   }
-#define NB_ACC(c, q, ev, b)                                    \
+#define NB_ACC(s, q, ev, b)                                    \
   {                                                            \
     const float a_ = fabsf(q);                                 \
-    am_##c = (a_ < m1_##c) ? (1u << (b)) : am_##c;             \
-    m2_##c = __builtin_amdgcn_fmed3f(a_, m1_##c, m2_##c);      \
-    m1_##c = bpdc_lane::absmin(q, m1_##c);                     \
-    sb_##c = __builtin_amdgcn_alignbit(sb_##c, __float_as_uint(q), 31); \
-    ep_##c ^= (ev);                                            \
+    am_##s = (a_ < m1_##s) ? (1u << (b)) : am_##s;             \
+    m2_##s = __builtin_amdgcn_fmed3f(a_, m1_##s, m2_##s);      \
+    m1_##s = bpdc_lane::absmin(q, m1_##s);                     \
+    sb_##s = __builtin_amdgcn_alignbit(sb_##s, __float_as_uint(q), 31); \
+    ep_##s ^= (ev);                                            \
   }
-// Complete check c (degree d, field at bit `off` of W[cw]): r signs =
+// Complete slot s (degree d, field at bit `off` of W[cw]): r signs =
 // s_c xor parity of all q signs xor own sign; stop-test parity into U.
-#define NB_FIN(c, cw, off, d)                                               \
+#define NB_FIN(s, cw, off, d)                                               \
   {                                                                         \
-    const u32 sc_ = __builtin_amdgcn_ubfe(S[(c) >> 5], (c) & 31, 1);        \
-    const u32 rs_ = ((u32)__builtin_popcount(sb_##c) ^ sc_) & 1u;          \
+    const u32 sc_ = __builtin_amdgcn_ubfe(S[(s) >> 5], (s) & 31, 1);        \
+    const u32 rs_ = ((u32)__builtin_popcount(sb_##s) ^ sc_) & 1u;          \
     const u32 rm_ = (0u - rs_) & ((1u << (d)) - 1u);                        \
-    const u32 f_ = (am_##c << (d)) | (sb_##c ^ rm_);                        \
+    const u32 f_ = (am_##s << (d)) | (sb_##s ^ rm_);                        \
     const u32 fm_ = ((1u << (2 * (d))) - 1u) << (off);                      \
     W[cw] = (W[cw] & ~fm_) | (f_ << (off));                                 \
-    A1[c] = alpha * m1_##c;                                                 \
-    A2[c] = alpha * m2_##c;                                                 \
-    U |= ep_##c ^ (sc_ << 31);                                              \
+    A1[s] = alpha * m1_##s;                                                 \
+    A2[s] = alpha * m2_##s;                                                 \
+    U |= ep_##s ^ (sc_ << 31);                                              \
   }
-#define NB_DEC(c, cw, op, sp) bpdc_lane::dec(A1[c], A2[c], W[cw], op, sp, SIGNMASK)
-#define NB_CUT(L, v) L = bpdc_lane::cutsel(L, C[(v) >> 5], (v) & 31, INFBITS)
-#define NB_STORE(v, L) myL[(v) * NB_STRIDE] = (L)
+#define NB_DEC(s, cw, op, sp) bpdc_lane::dec(A1[s], A2[s], W[cw], op, sp, SIGNMASK)
+#define NB_CUT(L, i) L = bpdc_lane::cutsel(L, C[(i) >> 5], (i) & 31, INFBITS)
+#define NB_STORE(i, L) myL[(i) * NB_STRIDE] = (L)
 #define NB_Q(L, r) bpdc_dev::sat((L) - (r), LS)
+#define NB_SWAPF(x) bpdc_lane::swapf(x)
+#define NB_SWAPU(x) bpdc_lane::swapu(x)
+#define NB_PICK(a, b) (isB ? (b) : (a))
 
-#if NB_POSTERIOR
-#define NB_LAM(v) (pass ? myLam2[(v) * NB_STRIDE] : lamp[v])
+#if NB_UNIFORM_PRIOR
+#define NB_LAM1(i) LAMU
 #else
-#define NB_LAM(v) (lamp[v])
+#define NB_LAM1(i) lamrow[i]
 #endif
-
+#if NB_POSTERIOR
+#define NB_LAM(i) (pass ? myLam2[(i) * NB_STRIDE] : NB_LAM1(i))
+#else
+#define NB_LAM(i) NB_LAM1(i)
+#endif
 
 extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a) {
   using namespace bpdc_lane;
-  __shared__ float sL[NB_N * NB_STRIDE];
+  __shared__ float sL[NB_ROWS * NB_STRIDE];
 #if NB_POSTERIOR
-  __shared__ float sLam2[NB_N * NB_STRIDE];
+  __shared__ float sLam2[NB_ROWS * NB_STRIDE];
 #endif
   __shared__ int sDptr[NB_MD + 1];
   __shared__ short sDcol[NB_DNNZ];
-  __shared__ u32 sCut[NB_NC32];
-  __shared__ float sLam[NB_N];
+  __shared__ u32 sCut[2][NB_RC32];
+#if !NB_UNIFORM_PRIOR
+  __shared__ float sLamRow[2][NB_ROWS];
+#endif
 
   const int lane = threadIdx.x;
+  const bool isB = NB_PAIRED && (lane & 1);
+  const int first_of_pair = NB_PAIRED ? (lane & ~1) : lane;
   for (int i = lane; i <= NB_MD; i += 64) sDptr[i] = a.d_row_ptr[i];
   for (int i = lane; i < NB_DNNZ; i += 64) sDcol[i] = (short)a.d_col[i];
-  for (int i = lane; i < NB_N; i += 64) sLam[i] = a.lam[i];
+#if !NB_UNIFORM_PRIOR
+  for (int i = lane; i < 2 * NB_ROWS; i += 64)
+    sLamRow[i / NB_ROWS][i % NB_ROWS] = a.lam[nb_row_col[i / NB_ROWS][i % NB_ROWS]];
+#endif
   __syncthreads();
 
   float* myL = sL + lane;
 #if NB_POSTERIOR
   float* myLam2 = sLam2 + lane;
 #endif
-  const u32 SIGNMASK = 0x80000000u, INFBITS = 0x7F800000u;
   const float LS = a.lsat;
   const float alpha = a.alpha;
-  const u64 below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const float LAMU = a.lam_uniform;
+  const u32 SIGNMASK = 0x80000000u, INFBITS = 0x7F800000u;
+  // lanes below the first lane of this lane's pair (for numbering new shots)
+  const u64 below = (first_of_pair == 0) ? 0ull : (~0ull >> (64 - first_of_pair));
+  const u64 leaders = NB_PAIRED ? 0x5555555555555555ull : ~0ull;
 
-  float A1[NB_M], A2[NB_M];
-  u32 W[NB_NWC], S[NB_SW32], C[NB_NC32];
+  float A1[NB_SLOTS], A2[NB_SLOTS];
+  u32 W[NB_NWC], S[NB_SW32], C[NB_RC32];
   long long shot = -1;
   int t = 0, pass = 0, it1 = 0;
   bool want = true, dead = false;
 
   for (;;) {
-    // ---- take new shots for idle lanes --------------------------------------------
-    const u64 need = __ballot(want && !dead);
+    // ---- take new shots for idle lanes (pairs) -----------------------------------------
+    const u64 need = __ballot(want && !dead) & leaders;
     if (need) {
       const int leader = __ffsll((long long)need) - 1;
       unsigned long long base = 0;
@@ -184,17 +220,24 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         if (my < a.B) {
           shot = my;
           const unsigned long long* sp = a.syn + my * NB_SW64;
+          u32 Sf[NB_SW32];
 #pragma unroll
           for (int w = 0; w < NB_SW32; ++w) {
             const unsigned long long x = sp[w >> 1];
-            S[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
+            Sf[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
           }
 #pragma unroll
-          for (int c = 0; c < NB_M; ++c) { A1[c] = 0.0f; A2[c] = 0.0f; }
+          for (int w = 0; w < NB_SW32; ++w) {
+            // lane B holds checks m/2.. : its syndrome bits start at m/2
+            const u32 sb = NB_PAIRED ? bits32<NB_SW32>(Sf, (NB_M / 2) + 32 * w) : Sf[w];
+            S[w] = isB ? sb : Sf[w];
+          }
+#pragma unroll
+          for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
 #pragma unroll
           for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
 #pragma unroll
-          for (int w = 0; w < NB_NC32; ++w) C[w] = 0u;
+          for (int w = 0; w < NB_RC32; ++w) C[w] = 0u;
           t = 0;
           pass = 0;
           it1 = 0;
@@ -208,14 +251,18 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
     if (__ballot(shot >= 0) == 0) break;
 
     // ---- one sweep: variable half of iteration t, check half of iteration t+1 -----
-    // Priors are read from LDS (a broadcast read per column) through an offset
-    // the compiler cannot prove constant, so that they are not hoisted out of
-    // the loop into n registers.
+#if !NB_UNIFORM_PRIOR
+    // priors read from LDS through an offset the compiler cannot prove
+    // constant, so that they are not hoisted out of the loop into registers
     int zoff;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
-    const float* lamp = sLam + zoff;
+    const float* lamrow = &sLamRow[isB ? 1 : 0][0] + zoff;
+#endif
     u32 U = 0u;
     NB_SWEEP();
+#if NB_PAIRED
+    U |= NB_SWAPU(U);
+#endif
 
     const bool conv = (U >> 31) == 0u;
     const int T = pass ? a.T2 : a.T1;
@@ -224,13 +271,13 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
     const bool finish = done && !to_dc;
 
     if (__ballot(done)) {
-      // ---- degeneracy cutting for each lane whose first pass failed -------------------
-      u64 dcm = __ballot(to_dc);
+      // ---- degeneracy cutting for each shot whose first pass failed -------------------
+      u64 dcm = __ballot(to_dc) & leaders;
       while (dcm) {
         const int src = __ffsll((long long)dcm) - 1;
         dcm &= dcm - 1;
         const long long sshot = __shfl(shot, src);
-        for (int w = lane; w < NB_NC32; w += 64) sCut[w] = 0u;
+        for (int w = lane; w < 2 * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
         __syncthreads();
         for (int h = lane; h < NB_MD; h += 64) {
           const int b0 = sDptr[h], deg = sDptr[h + 1] - b0;
@@ -238,44 +285,57 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
           float vals[NB_DMAXROW];
           for (int k = 0; k < deg; ++k) {
             cols[k] = sDcol[b0 + k];
-            vals[k] = bpdc_dev::sat(sL[cols[k] * NB_STRIDE + src], LS);
+            const int cr = nb_col_row[cols[k]];
+            vals[k] = bpdc_dev::sat(sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)], LS);
           }
           if (deg > 0) {
-            const int pick = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest,
-                                                           a.seed, (u64)(a.shot_offset + sshot), (u64)h);
-            atomicOr(&sCut[pick >> 5], 1u << (pick & 31));
+            const int pick = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
+                                                           (u64)(a.shot_offset + sshot), (u64)h);
+            const int pr = nb_col_row[pick];
+            atomicOr(&sCut[pr & 1][(pr >> 1) >> 5], 1u << ((pr >> 1) & 31));
           }
         }
         __syncthreads();
 #if NB_POSTERIOR
-        for (int v = lane; v < NB_N; v += 64) {
-          const bool cv = (sCut[v >> 5] >> (v & 31)) & 1u;
-          sLam2[v * NB_STRIDE + src] = cv ? __builtin_huge_valf() : bpdc_dev::sat(sL[v * NB_STRIDE + src], LS);
+        for (int u = lane; u < NB_N; u += 64) {
+          const int cr = nb_col_row[u];
+          const int r = cr >> 1, hb = cr & 1;
+          const bool cv = (sCut[hb][r >> 5] >> (r & 31)) & 1u;
+          const float x = sL[r * NB_STRIDE + src + hb];
+          sLam2[r * NB_STRIDE + src + hb] = cv ? __builtin_huge_valf() : bpdc_dev::sat(x, LS);
         }
 #endif
-        if (lane == src) {
+        if (lane == src || (NB_PAIRED && lane == src + 1)) {
 #pragma unroll
-          for (int w = 0; w < NB_NC32; ++w) C[w] = sCut[w];
+          for (int w = 0; w < NB_RC32; ++w) C[w] = sCut[isB ? 1 : 0][w];
         }
         __syncthreads();
       }
       // ---- output of finished shots ---------------------------------------------------
-      u64 fm = __ballot(finish);
+      u64 fm = __ballot(finish) & leaders;
       while (fm) {
         const int src = __ffsll((long long)fm) - 1;
         fm &= fm - 1;
         const long long sshot = __shfl(shot, src);
-#pragma unroll
-        for (int w = 0; w < NB_NW64; ++w) {
-          const int v = w * 64 + lane;
-          const bool e = (v < NB_N) && (sL[v * NB_STRIDE + src] <= 0.0f);
-          const u64 word = __ballot(e);
-          if (lane == 0) a.corr[sshot * NB_NW64 + w] = word;
-        }
         const int spass = __shfl(pass, src);
         const bool sconv = __shfl((int)conv, src) != 0;
         const int st = __shfl(t, src);
         const int sit1 = __shfl(it1, src);
+#pragma unroll
+        for (int w = 0; w < NB_NW64; ++w) {
+          const int u = w * 64 + lane;
+          float x = 1.0f;
+          if (u < NB_N) {
+            const int cr = nb_col_row[u];
+            x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
+          }
+          const u64 word = __ballot(x <= 0.0f);
+          const u64 cword = __ballot(spass && x == __builtin_huge_valf());
+          if (lane == 0) {
+            a.corr[sshot * NB_NW64 + w] = word;
+            if (a.cut) a.cut[sshot * NB_NW64 + w] = cword;
+          }
+        }
         if (lane == 0) {
           a.flags[sshot] = (unsigned char)((sconv ? 1 : 0) | (spass ? 2 : 0));
           if (a.iters) {
@@ -283,24 +343,17 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
             a.iters[2 * sshot + 1] = (short)(spass ? st : 0);
           }
         }
-        if (a.cut) {
-#pragma unroll
-          for (int w = 0; w < NB_NW64; ++w) {
-            const u32 lo = (2 * w < NB_NC32) ? __shfl(C[(2 * w < NB_NC32) ? 2 * w : 0], src) : 0u;
-            const u32 hi = (2 * w + 1 < NB_NC32) ? __shfl(C[(2 * w + 1 < NB_NC32) ? 2 * w + 1 : 0], src) : 0u;
-            if (lane == 0) a.cut[sshot * NB_NW64 + w] = spass ? (((u64)hi << 32) | lo) : 0ull;
-          }
-        }
         if (a.post) {
-          for (int v = lane; v < NB_N; v += 64) {
-            const float x = sL[v * NB_STRIDE + src];
-            a.post[sshot * NB_N + v] = (x == __builtin_huge_valf()) ? x : bpdc_dev::sat(x, LS);
+          for (int u = lane; u < NB_N; u += 64) {
+            const int cr = nb_col_row[u];
+            const float x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
+            a.post[sshot * NB_N + u] = (x == __builtin_huge_valf()) ? x : bpdc_dev::sat(x, LS);
           }
         }
       }
       if (to_dc) {
 #pragma unroll
-        for (int c = 0; c < NB_M; ++c) { A1[c] = 0.0f; A2[c] = 0.0f; }
+        for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
 #pragma unroll
         for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
         it1 = t;

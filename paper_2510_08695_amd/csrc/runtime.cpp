@@ -235,20 +235,26 @@ struct LaneArgsHost {
   float alpha;
   float lsat;
   float tie_eps;
+  float lam_uniform;
   int T1;
   int T2;
   int stop;
   int tie_lowest;
-  int pad_;
   unsigned long long seed;
 };
+
+bool uniform_prior(const bpdc_code_s* c) {
+  for (float x : c->lam)
+    if (x != c->lam[0]) return false;
+  return true;
+}
 
 bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) {
   std::string why;
   if (!bpdc::lane_eligible(c->g, posterior, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  bpdc_status st = lane_code_object(bpdc::lane_spec(c->g, posterior), &image, &lk->cache_path);
+  bpdc_status st = lane_code_object(bpdc::lane_spec(c->g, posterior, uniform_prior(c)), &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
   HIP_TRY(hipModuleLoadData(&lk->mod, image.data()));
   HIP_TRY(hipModuleGetFunction(&lk->fn, lk->mod, "bpdc_lane_kernel"));
@@ -282,11 +288,11 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   a.alpha = p->kp.alpha;
   a.lsat = p->kp.lsat;
   a.tie_eps = p->kp.tie_eps;
+  a.lam_uniform = c->lam[0];
   a.T1 = p->kp.T1;
   a.T2 = p->kp.T2;
   a.stop = p->kp.stop;
   a.tie_lowest = p->kp.tie_lowest;
-  a.pad_ = 0;
   a.seed = p->kp.seed;
   void* args[] = {&a};
   const int64_t want = (io.B + 63) / 64;
@@ -573,7 +579,7 @@ bpdc_status bpdc_code_info(bpdc_code c, int32_t* n, int32_t* m, int32_t* md, int
   return BPDC_OK;
 }
 
-bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior) {
+bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior, int32_t uniform_prior) {
   std::string why;
   if (!H || !D || !csr_ok(H, &why) || !csr_ok(D, &why) || H->cols != D->cols)
     return fail(BPDC_ERR_INVALID_ARG, "bad CSR: %s", why.c_str());
@@ -593,7 +599,7 @@ bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t p
   if (!bpdc::lane_eligible(g, posterior != 0, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  return lane_code_object(bpdc::lane_spec(g, posterior != 0), &image, nullptr);
+  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0), &image, nullptr);
 }
 
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
