@@ -49,6 +49,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--workload", default="bb144",
+                    choices=["bb144", "toric6", "phen", "hgp64", "wms"],
+                    help="bb144: the headline configuration (default); the others are the "
+                         "secondary configurations, each printing its own JSON line")
+    ap.add_argument("--dem-form", default="open", choices=["open", "paper"])
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel that "
                          "calibrates hardware byte counters)")
@@ -64,6 +70,9 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload != "bb144":
+        {"toric6": run_toric6, "phen": run_phen, "hgp64": run_hgp64, "wms": run_wms}[args.workload](args)
+        return
     p, B = args.p, args.shots
     code = synth.bb_code("bb144", p=p)
     shots = synth.make_shots(code, B, 2000 + round(100 * p))
@@ -175,6 +184,246 @@ def main():
                                   "ler_on_sample": fails / done,
                                   "gpu_ler_on_sample": float(fail[:done].mean())}
     print(json.dumps(result), flush=True)
+
+
+# ---------------------------------------------------------------------------------------------
+# secondary configurations (each prints one JSON line)
+
+
+def _timed(fn, steps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _oracle_sample(code, syndromes, errors, op, seconds, chunk=2000):
+    import oracle
+    import synth
+    cores = len(os.sched_getaffinity(0))
+    done, el, fails = 0, 0.0, 0
+    while el < seconds and done < len(syndromes):
+        hi = min(len(syndromes), done + chunk)
+        t = time.perf_counter()
+        o = oracle.decode(code, syndromes[done:hi], op, precision="f64", shot_offset=done, want_post=False,
+                          threads=cores)
+        el += time.perf_counter() - t
+        f = ((o["flags"] & 1) == 0)
+        if code.O is not None:
+            f |= synth.residual_is_logical(errors[done:hi] ^ o["ehat"], code.O)
+        fails += int(f.sum())
+        done = hi
+    return {"value": done / el, "unit": "shots/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done} shots, float64 oracle, {cores} OpenMP threads", "ler_on_sample": fails / done,
+            "shots": done}
+
+
+def _ler(code, errors, corr_words, flags):
+    import synth
+    ehat = synth.unpack_bits(corr_words, code.n)
+    fail = (flags & 1) == 0
+    if code.O is not None:
+        fail |= synth.residual_is_logical(errors ^ ehat, code.O)
+    k = int(fail.sum())
+    lo, hi = wilson(k, len(flags))
+    return k / len(flags), [lo, hi]
+
+
+def _single(args, code, B, seed, prm, workload, metric, kernel):
+    import torch
+    import paper_2510_08695_amd as P
+    import synth
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_helpers import oracle_params
+    shots = synth.make_shots(code, B, seed)
+    c = P.Code.from_problem(code)
+    plan = P.Plan([c], prm, kernel=kernel)
+    syn = torch.from_numpy(synth.pack_bits(shots.syndromes).view(np.int64)).cuda()
+    out = plan.decode(syn, want_iters=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms = _timed(lambda: plan.decode(syn, out=out), args.steps, stream)
+    flags = out["flags"].cpu().numpy()
+    iters = out["iters"].cpu().numpy().astype(np.int64)
+    ler, ci = _ler(code, shots.errors, out["corr"].cpu().numpy().view(np.uint64), flags)
+    n_dc = int(((flags & 2) != 0).sum())
+    ops = OPS_PER_EDGE_ITER * code.H.nnz * int(iters.sum()) + OPS_PER_DC_ENTRY * code.D.nnz * n_dc
+    res = {"metric": metric, "value": B / (ms / 1e3), "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
+           "ms_per_step": ms, "dtype": "f32", "data": "synthetic", "config": {"workload": workload,
+           "shots_per_step": B, "plan": plan.info(0)},
+           "ler": ler, "ler_ci95": ci, "dc_rate": n_dc / B, "mean_iters": float(iters.sum()) / B,
+           "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS}}
+    if not args.no_plain:
+        pplan = P.Plan([c], prm, kernel=P.KERNEL_PLAIN)
+        pout = pplan.decode(syn)
+        pms = _timed(lambda: pplan.decode(syn, out=pout), 1, stream)
+        res["plain"] = {"shots_per_s": B / (pms / 1e3), "speedup_fused_vs_plain": pms / ms,
+                        "identical_outputs": bool(torch.equal(pout["corr"], out["corr"]) and
+                                                  torch.equal(pout["flags"], out["flags"]))}
+    if not args.no_cpu:
+        sp = "posterior" if prm.second_pass_prior == P.PRIOR_POSTERIOR else "channel"
+        cb = _oracle_sample(code, shots.syndromes, shots.errors, oracle_params(prm, sp), args.cpu_seconds)
+        k = cb.pop("shots")
+        cb["gpu_ler_on_sample"] = _ler(code, shots.errors[:k], out["corr"].cpu().numpy().view(np.uint64)[:k],
+                                       flags[:k])[0]
+        res["cpu_baseline"] = cb
+    return res
+
+
+def run_toric6(args):
+    import paper_2510_08695_amd as P
+    import synth
+    code = synth.toric_code(6, p=0.05)
+    prm = P.Params(max_iter=(50, 50), alpha=0.625, second_pass_prior=P.PRIOR_POSTERIOR, seed=1)
+    res = _single(args, code, 10_000, 1, prm, "toric L=6 code capacity p=0.05, 1e4 shots, alpha=0.625, "
+                  "T=50+50, posterior second pass", "shots/s BP+DC toric L=6 p=0.05", P.KERNEL_LANE)
+    print(json.dumps(res), flush=True)
+
+
+def run_phen(args):
+    import paper_2510_08695_amd as P
+    import synth
+    final = args.dem_form == "paper"
+    code = synth.phenomenological_dem(synth.bb_code("bb288"), 18, 0.003, 0.003, final)
+    prm = P.Params(max_iter=(1000, 1000), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=3)
+    B = min(args.shots, 100_000)
+    res = _single(args, code, B, 3, prm, f"BB[[288,12,18]] phenomenological T=18 p=0.003 ({args.dem_form} "
+                  f"time boundary, {code.H.rows}x{code.n}), {B} shots, alpha=0.625, T=1000+1000",
+                  "shots/s BP+DC phenomenological BB288 T=18", P.KERNEL_GROUP)
+    print(json.dumps(res), flush=True)
+
+
+def run_hgp64(args):
+    import torch
+    import paper_2510_08695_amd as P
+    import synth
+    codes = synth.hgp_batch_codes(64, 4000, 0.03, with_logicals=False)
+    rng = np.random.default_rng(4)
+    counts = rng.poisson(2000, size=len(codes))
+    code_of_shot = np.concatenate([np.full(k, i, np.int32) for i, k in enumerate(counts)])
+    rng.shuffle(code_of_shot)
+    B = len(code_of_shot)
+    rows, per = [None] * B, []
+    for i, c in enumerate(codes):
+        idx = np.nonzero(code_of_shot == i)[0]
+        sh = synth.make_shots(c, len(idx), 4100 + i)
+        per.append((idx, sh))
+        packed = synth.pack_bits(sh.syndromes)
+        for k, b in enumerate(idx):
+            rows[b] = packed[k]
+    syn = torch.from_numpy(np.concatenate(rows).view(np.int64)).cuda()
+    prm = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=4)
+    t = time.perf_counter()
+    handles = [P.Code.from_problem(c) for c in codes]
+    plan = P.Plan(handles, prm, kernel=P.KERNEL_GROUP)
+    plan_s = time.perf_counter() - t
+    cos = torch.from_numpy(code_of_shot).cuda()
+    so, co, sw, nw = plan.multi_buffers(cos)
+    corr = torch.empty(nw, dtype=torch.int64, device="cuda")
+    flags = torch.empty(B, dtype=torch.uint8, device="cuda")
+    iters = torch.empty((B, 2), dtype=torch.int16, device="cuda")
+    plan.capture_multi(cos, syn, so, corr, co, flags, iters)
+    stream = torch.cuda.current_stream()
+    ms = _timed(lambda: plan.graph_launch(), args.steps, stream)
+    it = iters.cpu().numpy().astype(np.int64)
+    fl = flags.cpu().numpy()
+    ops = 0
+    for i, c in enumerate(codes):
+        idx = per[i][0]
+        ops += OPS_PER_EDGE_ITER * c.H.nnz * int(it[idx].sum()) + OPS_PER_DC_ENTRY * c.D.nnz * int(((fl[idx] & 2) != 0).sum())
+    res = {"metric": "shots/s BP+DC, 64 uneven HGP codes in one graph-captured persistent launch", "value": B / (ms / 1e3),
+           "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "ms_per_step": ms, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"64 hypergraph-product codes of random (3,4)-regular codes, n in "
+                                  f"[{min(c.n for c in codes)}, {max(c.n for c in codes)}], p=0.03, "
+                                  f"Poisson(2000) shots each ({B} total), T=100+100",
+                      "plan_seconds": plan_s, "tile": {"threads": plan.info(int(np.argmax([c.n for c in codes])))["threads"]}},
+           "dc_rate": float(((fl & 2) != 0).mean()), "mean_iters": float(it.sum()) / B,
+           "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS}}
+    if not args.no_plain:
+        # plain per-code launches over the same shots
+        pplan = P.Plan(handles, prm, kernel=P.KERNEL_PLAIN)
+        subs = []
+        for i, c in enumerate(codes):
+            idx = per[i][0]
+            s_i = torch.from_numpy(synth.pack_bits(per[i][1].syndromes).view(np.int64)).cuda()
+            subs.append((i, s_i))
+        def run_plain():
+            for i, s_i in subs:
+                pplan.decode(s_i, code=i)
+        pms = _timed(run_plain, 1, stream)
+        res["plain"] = {"shots_per_s": B / (pms / 1e3), "speedup_batched_vs_plain": pms / ms}
+    print(json.dumps(res), flush=True)
+
+
+def run_wms(args):
+    import torch
+    import paper_2510_08695_amd as P
+    import synth
+    code = synth.bb_code("bb144", p=0.05)
+    prm = P.Params(max_iter=(25, 25), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, stop_on_converge=False,
+                   seed=5)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    f = P.weighted_bpdc(plan, ckpt_every=5)
+    E = code.H.nnz
+    w = torch.full((2 * E,), 0.625, dtype=torch.float32, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([w], lr=1e-3)
+    bce = lambda L, e: e * torch.nn.functional.softplus(L) + (1 - e) * torch.nn.functional.softplus(-L)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    step_ms, losses = [], []
+    for step in range(args.train_steps):
+        sh = synth.make_shots(code, 4096, 5000 + step)
+        syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
+        e = torch.from_numpy(sh.errors.astype(np.float32)).cuda()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        post, cut, flags = f(w, syn)
+        dc = ((flags & 2) != 0).float()[:, None]
+        cutb = torch.from_numpy(synth.unpack_bits(cut.cpu().numpy().view(np.uint64), code.n)).cuda().float()
+        keep2 = dc * (1 - cutb)
+        L2 = torch.where(keep2 > 0, post[1], torch.zeros_like(post[1]))
+        loss = (bce(post[0], e).sum() + (bce(L2, e) * keep2).sum()) / e.shape[0]
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        step_ms.append(a.elapsed_time(b))
+        losses.append(loss.item())
+    train_s = time.perf_counter() - t0
+
+    def evaluate(wv, B=1_000_000, seed=5999):
+        sh = synth.make_shots(code, B, seed)
+        syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
+        fails = 0
+        for lo in range(0, B, 250_000):
+            out = plan.wms_forward(wv.detach().contiguous(), syn[lo:lo + 250_000], shot_offset=lo)
+            ehat = (out["post"][1] <= 0).cpu().numpy().astype(np.uint8)
+            fl = out["flags"].cpu().numpy()
+            f = ((fl & 1) == 0) | synth.residual_is_logical(sh.errors[lo:lo + 250_000] ^ ehat, code.O)
+            fails += int(f.sum())
+        k = fails
+        return k / B, list(wilson(k, B))
+
+    ler_init, ci_init = evaluate(torch.full((2 * E,), 0.625, device="cuda"))
+    ler_trained, ci_trained = evaluate(w)
+    res = {"metric": "weighted min-sum BP+DC on BB[[144,12,12]] p=0.05: LER trained vs 0.625 at 25+25 iterations",
+           "value": ler_trained, "unit": "LER", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "BB144 code capacity p=0.05, batch 4096, 25+25 unrolled iterations, checkpoint "
+                                  "every 5, Adam lr 1e-3", "train_steps": args.train_steps},
+           "ler_untrained": ler_init, "ler_untrained_ci95": ci_init, "ler_trained_ci95": ci_trained,
+           "train_seconds": train_s, "train_step_ms_median": float(np.median(step_ms)),
+           "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-10:]))}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

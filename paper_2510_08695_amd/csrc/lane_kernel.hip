@@ -149,7 +149,11 @@ __device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
 #define NB_DEC(s, cw, op, sp) bpdc_lane::dec(A1[s], A2[s], W[cw], op, sp, SIGNMASK)
 #define NB_CUT(L, i) L = bpdc_lane::cutsel(L, C[(i) >> 5], (i) & 31, INFBITS)
 #define NB_STORE(i, L) myL[(i) * NB_STRIDE] = (L)
-#define NB_Q(L, r) bpdc_dev::sat((L) - (r), LS)
+// q = L - r without the clamp to [-lsat, lsat]: q enters the check state only
+// through its sign bit and through min / median operations against minima
+// that start at lsat, and clamping changes neither (|q| >= lsat leaves every
+// minimum, argmin and second minimum as they are; the sign is kept).
+#define NB_Q(L, r) ((L) - (r))
 #define NB_SWAPF(x) bpdc_lane::swapf(x)
 #define NB_SWAPU(x) bpdc_lane::swapu(x)
 #define NB_PICK(a, b) (isB ? (b) : (a))
@@ -174,6 +178,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   __shared__ int sDptr[NB_MD + 1];
   __shared__ short sDcol[NB_DNNZ];
   __shared__ u32 sCut[2][NB_RC32];
+  __shared__ short sColRow[NB_N];
 #if !NB_UNIFORM_PRIOR
   __shared__ float sLamRow[2][NB_ROWS];
 #endif
@@ -183,6 +188,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   const int first_of_pair = NB_PAIRED ? (lane & ~1) : lane;
   for (int i = lane; i <= NB_MD; i += 64) sDptr[i] = a.d_row_ptr[i];
   for (int i = lane; i < NB_DNNZ; i += 64) sDcol[i] = (short)a.d_col[i];
+  for (int i = lane; i < NB_N; i += 64) sColRow[i] = nb_col_row[i];
 #if !NB_UNIFORM_PRIOR
   for (int i = lane; i < 2 * NB_ROWS; i += 64)
     sLamRow[i / NB_ROWS][i % NB_ROWS] = a.lam[nb_row_col[i / NB_ROWS][i % NB_ROWS]];
@@ -285,20 +291,20 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
           float vals[NB_DMAXROW];
           for (int k = 0; k < deg; ++k) {
             cols[k] = sDcol[b0 + k];
-            const int cr = nb_col_row[cols[k]];
+            const int cr = sColRow[cols[k]];
             vals[k] = bpdc_dev::sat(sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)], LS);
           }
           if (deg > 0) {
             const int pick = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
                                                            (u64)(a.shot_offset + sshot), (u64)h);
-            const int pr = nb_col_row[pick];
+            const int pr = sColRow[pick];
             atomicOr(&sCut[pr & 1][(pr >> 1) >> 5], 1u << ((pr >> 1) & 31));
           }
         }
         __syncthreads();
 #if NB_POSTERIOR
         for (int u = lane; u < NB_N; u += 64) {
-          const int cr = nb_col_row[u];
+          const int cr = sColRow[u];
           const int r = cr >> 1, hb = cr & 1;
           const bool cv = (sCut[hb][r >> 5] >> (r & 31)) & 1u;
           const float x = sL[r * NB_STRIDE + src + hb];
@@ -326,7 +332,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
           const int u = w * 64 + lane;
           float x = 1.0f;
           if (u < NB_N) {
-            const int cr = nb_col_row[u];
+            const int cr = sColRow[u];
             x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
           }
           const u64 word = __ballot(x <= 0.0f);
@@ -345,7 +351,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         }
         if (a.post) {
           for (int u = lane; u < NB_N; u += 64) {
-            const int cr = nb_col_row[u];
+            const int cr = sColRow[u];
             const float x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
             a.post[sshot * NB_N + u] = (x == __builtin_huge_valf()) ? x : bpdc_dev::sat(x, LS);
           }
