@@ -28,6 +28,33 @@ OPS_PER_EDGE_ITER = 8               # algorithmic VALU ops per Tanner edge per i
 OPS_PER_DC_ENTRY = 2                # per nonzero of D on shots that run DC
 
 
+LANE_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/lane_kernel.hip",
+                "paper_2510_08695_amd/csrc/lane_spec.cpp")
+LANE_COUNTERS = "profiles/bpdc_lane_kernel_bb144_p005_1e6_counters.md"
+
+
+def lane_traffic():
+    """HBM bytes per lane-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a copy of known
+    size), or None once the kernel source differs from the one profiled."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in LANE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    try:
+        with open(os.path.join(ROOT, LANE_COUNTERS)) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(": ")
+                vals[k] = v
+    except OSError:
+        return None
+    if vals.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def wilson(k: int, n: int, z: float = 1.96):
     if n == 0:
         return (0.0, 0.0)
@@ -129,8 +156,11 @@ def main():
         "mean_iters": float(iters.sum()) / B,
     }
     achieved = ops_per_step / (launch_ms / 1e3)
+    traffic = lane_traffic() if B == 1_000_000 and p == 0.05 else None
     result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                          "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                          "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                          "traffic_unit": "bytes per launch", "algorithmic_bytes": B * (8 * ((code.H.rows + 63) // 64) +
+                                                                                      8 * ((code.n + 63) // 64) + 1),
                           "launch_ms": launch_ms, "ops_per_launch": ops_per_step}
 
     if args.copy_probe_mib:
