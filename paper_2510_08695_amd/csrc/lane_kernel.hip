@@ -58,9 +58,17 @@ struct LaneArgs {
   int stop;
   int tie_lowest;
   unsigned long long seed;
+  float a1_init;                  // alpha * lambda: check state after a first iteration (equal priors)
+  float a2_init1;                 // alpha * lsat: its second minimum for a check of degree 1
+  int skip0;                      // start first passes from that state (equal priors, 0 < lambda < lsat)
 };
 
-#define NB_STRIDE 65  // LDS row stride (floats) of the [row][lane] posterior array
+// Posteriors in LDS as [column][shot slot of the wave]: one slot per lane, or
+// per pair of lanes in the paired layout (lane B's columns are lane A's
+// shifted by NB_HALFOFF, so both lanes store with the same offsets).  The
+// strides 65 and 33 keep column-wise reads free of bank conflicts.
+#define NB_LSTR (NB_PAIRED ? 33 : 65)
+#define NB_CHUNK 32   // largest number of shots a wave claims at once
 
 namespace bpdc_lane {
 using bpdc_dev::u32;
@@ -148,7 +156,7 @@ __device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
   }
 #define NB_DEC(s, cw, op, sp) bpdc_lane::dec(A1[s], A2[s], W[cw], op, sp, SIGNMASK)
 #define NB_CUT(L, i) L = bpdc_lane::cutsel(L, C[(i) >> 5], (i) & 31, INFBITS)
-#define NB_STORE(i, L) myL[(i) * NB_STRIDE] = (L)
+#define NB_STORE(v, L) myL[(v) * NB_LSTR] = (L)
 // q = L - r without the clamp to [-lsat, lsat]: q enters the check state only
 // through its sign bit and through min / median operations against minima
 // that start at lsat, and clamping changes neither (|q| >= lsat leaves every
@@ -164,21 +172,22 @@ __device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
 #define NB_LAM1(i) lamrow[i]
 #endif
 #if NB_POSTERIOR
-#define NB_LAM(i) (pass ? myLam2[(i) * NB_STRIDE] : NB_LAM1(i))
+#define NB_LAM(i, v) (pass ? myLam2[(v) * NB_LSTR] : NB_LAM1(i))
 #else
-#define NB_LAM(i) NB_LAM1(i)
+#define NB_LAM(i, v) NB_LAM1(i)
 #endif
 
 extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a) {
   using namespace bpdc_lane;
-  __shared__ float sL[NB_ROWS * NB_STRIDE];
+  __shared__ float sL[NB_N * NB_LSTR];
 #if NB_POSTERIOR
-  __shared__ float sLam2[NB_ROWS * NB_STRIDE];
+  __shared__ float sLam2[NB_N * NB_LSTR];
 #endif
   __shared__ int sDptr[NB_MD + 1];
   __shared__ short sDcol[NB_DNNZ];
   __shared__ u32 sCut[2][NB_RC32];
   __shared__ short sColRow[NB_N];
+  __shared__ u32 sSyn[NB_CHUNK][NB_SW32];  // staged syndromes of the reservoir
 #if !NB_UNIFORM_PRIOR
   __shared__ float sLamRow[2][NB_ROWS];
 #endif
@@ -195,13 +204,15 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
 #endif
   __syncthreads();
 
-  float* myL = sL + lane;
+  const int sid = NB_PAIRED ? (lane >> 1) : lane;  // this lane's shot slot in sL
+  float* myL = sL + sid + (isB ? NB_HALFOFF * NB_LSTR : 0);
 #if NB_POSTERIOR
-  float* myLam2 = sLam2 + lane;
+  float* myLam2 = sLam2 + sid + (isB ? NB_HALFOFF * NB_LSTR : 0);
 #endif
   const float LS = a.lsat;
   const float alpha = a.alpha;
   const float LAMU = a.lam_uniform;
+  const float A1I = a.a1_init, A2I1 = a.a2_init1;
   const u32 SIGNMASK = 0x80000000u, INFBITS = 0x7F800000u;
   // lanes below the first lane of this lane's pair (for numbering new shots)
   const u64 below = (first_of_pair == 0) ? 0ull : (~0ull >> (64 - first_of_pair));
@@ -212,26 +223,64 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   long long shot = -1;
   int t = 0, pass = 0, it1 = 0;
   bool want = true, dead = false;
+  // the wave's reservoir of claimed shots (wave-uniform)
+  long long rlo = 0, rhi = 0, sbase = 0, seen = 0;
+  bool exhausted = false;
 
   for (;;) {
     // ---- take new shots for idle lanes (pairs) -----------------------------------------
-    const u64 need = __ballot(want && !dead) & leaders;
-    if (need) {
-      const int leader = __ffsll((long long)need) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)__popcll(need));
-      base = __shfl(base, leader);
-      if (want && !dead) {
-        const long long my = (long long)base + __popcll(need & below);
-        if (my < a.B) {
-          shot = my;
-          const unsigned long long* sp = a.syn + my * NB_SW64;
-          u32 Sf[NB_SW32];
+    // Shots come from the wave's reservoir [rlo, rhi), a chunk of consecutive
+    // shot indices claimed with one atomic, whose syndromes were staged in LDS
+    // when it was claimed: a refill waits neither for the counter nor for
+    // HBM.  The chunk shrinks as the batch runs out (a fraction of what was
+    // left at the wave's last claim), so that few claimed shots are still
+    // waiting when other waves already idle.
+    u64 need = __ballot(want && !dead) & leaders;
+    while (need) {
+      if (rlo == rhi) {
+        if (exhausted) {
+          if (want) {
+            dead = true;
+            shot = -1;
+            want = false;
+          }
+          break;
+        }
+        const long long left = a.B - seen;
+        long long c = left / (2 * (long long)gridDim.x);
+        c = c < 1 ? 1 : (c > NB_CHUNK ? NB_CHUNK : c);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)c);
+        // uniform across the wave: read from lane 0 into scalar registers
+        const long long b0 = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+                                         (unsigned)__builtin_amdgcn_readfirstlane((int)base));
+        seen = b0 + c;
+        if (b0 >= a.B) {
+          exhausted = true;
+          continue;
+        }
+        rlo = b0;
+        rhi = b0 + c < a.B ? b0 + c : a.B;
+        if (lane < rhi - rlo) {
+          const unsigned long long* sp = a.syn + (rlo + lane) * NB_SW64;
 #pragma unroll
           for (int w = 0; w < NB_SW32; ++w) {
             const unsigned long long x = sp[w >> 1];
-            Sf[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
+            sSyn[lane][w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
           }
+        }
+        __syncthreads();
+        sbase = rlo;
+      }
+      const long long avail = rhi - rlo;
+      if ((need >> first_of_pair) & 1ull) {
+        const long long rank = __popcll(need & below);
+        if (rank < avail) {
+          const long long my = rlo + rank;
+          shot = my;
+          u32 Sf[NB_SW32];
+#pragma unroll
+          for (int w = 0; w < NB_SW32; ++w) Sf[w] = sSyn[my - sbase][w];
 #pragma unroll
           for (int w = 0; w < NB_SW32; ++w) {
             // lane B holds checks m/2.. : its syndrome bits start at m/2
@@ -239,20 +288,29 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
             S[w] = isB ? sb : Sf[w];
           }
 #pragma unroll
-          for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
-#pragma unroll
-          for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
-#pragma unroll
           for (int w = 0; w < NB_RC32; ++w) C[w] = 0u;
-          t = 0;
+#if NB_UNIFORM_PRIOR
+          if (a.skip0) {
+            // the first iteration's check half, written directly
+            NB_INIT1();
+            t = 1;
+          } else
+#endif
+          {
+#pragma unroll
+            for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
+#pragma unroll
+            for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
+            t = 0;
+          }
           pass = 0;
           it1 = 0;
-        } else {
-          dead = true;
-          shot = -1;
+          want = false;
         }
-        want = false;
       }
+      const long long cnt = __popcll(need);
+      rlo += cnt < avail ? cnt : avail;
+      need = __ballot(want && !dead) & leaders;
     }
     if (__ballot(shot >= 0) == 0) break;
 
@@ -281,6 +339,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
       u64 dcm = __ballot(to_dc) & leaders;
       while (dcm) {
         const int src = __ffsll((long long)dcm) - 1;
+        const int ssid = NB_PAIRED ? (src >> 1) : src;
         dcm &= dcm - 1;
         const long long sshot = __shfl(shot, src);
         for (int w = lane; w < 2 * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
@@ -291,8 +350,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
           float vals[NB_DMAXROW];
           for (int k = 0; k < deg; ++k) {
             cols[k] = sDcol[b0 + k];
-            const int cr = sColRow[cols[k]];
-            vals[k] = bpdc_dev::sat(sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)], LS);
+            vals[k] = bpdc_dev::sat(sL[cols[k] * NB_LSTR + ssid], LS);
           }
           if (deg > 0) {
             const int pick = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
@@ -307,8 +365,8 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
           const int cr = sColRow[u];
           const int r = cr >> 1, hb = cr & 1;
           const bool cv = (sCut[hb][r >> 5] >> (r & 31)) & 1u;
-          const float x = sL[r * NB_STRIDE + src + hb];
-          sLam2[r * NB_STRIDE + src + hb] = cv ? __builtin_huge_valf() : bpdc_dev::sat(x, LS);
+          const float x = sL[u * NB_LSTR + ssid];
+          sLam2[u * NB_LSTR + ssid] = cv ? __builtin_huge_valf() : bpdc_dev::sat(x, LS);
         }
 #endif
         if (lane == src || (NB_PAIRED && lane == src + 1)) {
@@ -321,6 +379,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
       u64 fm = __ballot(finish) & leaders;
       while (fm) {
         const int src = __ffsll((long long)fm) - 1;
+        const int ssid = NB_PAIRED ? (src >> 1) : src;
         fm &= fm - 1;
         const long long sshot = __shfl(shot, src);
         const int spass = __shfl(pass, src);
@@ -331,10 +390,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         for (int w = 0; w < NB_NW64; ++w) {
           const int u = w * 64 + lane;
           float x = 1.0f;
-          if (u < NB_N) {
-            const int cr = sColRow[u];
-            x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
-          }
+          if (u < NB_N) x = sL[u * NB_LSTR + ssid];
           const u64 word = __ballot(x <= 0.0f);
           const u64 cword = __ballot(spass && x == __builtin_huge_valf());
           if (lane == 0) {
@@ -351,8 +407,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         }
         if (a.post) {
           for (int u = lane; u < NB_N; u += 64) {
-            const int cr = sColRow[u];
-            const float x = sL[(cr >> 1) * NB_STRIDE + src + (cr & 1)];
+            const float x = sL[u * NB_LSTR + ssid];
             a.post[sshot * NB_N + u] = (x == __builtin_huge_valf()) ? x : bpdc_dev::sat(x, LS);
           }
         }

@@ -23,6 +23,7 @@
 #include "lane_spec.h"
 
 #include <algorithm>
+#include <cstdint>
 #include <map>
 #include <numeric>
 #include <sstream>
@@ -179,7 +180,8 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
     << "\n#define NB_SLOTS " << nslots << "\n#define NB_ROWS " << nrows << "\n#define NB_RC32 "
     << (nrows + 31) / 32 << "\n#define NB_NWC " << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1)
     << "\n#define NB_DMAXROW " << std::max(1, max_deg(g.drows)) << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0)
-    << "\n#define NB_PAIRED " << (paired ? 1 : 0) << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0)
+    << "\n#define NB_PAIRED " << (paired ? 1 : 0) << "\n#define NB_HALFOFF " << (paired ? pr.block / 2 : 0)
+    << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0)
     << "\n";
   // column -> (row, lane B?) map for the cooperative DC / output code, and the
   // column of lane B at each row
@@ -205,7 +207,7 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
   for (int i : order) {
     const auto& e = ev[i];
     const int dv = (int)e.size();
-    o << "{ float L = NB_LAM(" << i << "); \\\n";
+    o << "{ float L = NB_LAM(" << i << ", " << row_col[i] << "); \\\n";
     for (int j = 0; j < dv; ++j) {
       const int s = e[j].slot, d = sdeg[s], b = d - 1 - pos[i][j];
       o << "const float r" << j << " = " << (e[j].remote ? "NB_SWAPF(" : "(") << "NB_DEC(" << s << ", " << cw[s]
@@ -224,7 +226,7 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
       if (perm[p] == p) o << "L = L + r" << p << "; \\\n";
       else o << "L = L + NB_PICK(r" << p << ", r" << perm[p] << "); \\\n";
     }
-    o << "NB_CUT(L, " << i << "); NB_STORE(" << i << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
+    o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
     bool any_remote = false;
     for (int j = 0; j < dv; ++j) any_remote |= e[j].remote != 0;
     if (any_remote) o << "const u32 evx = NB_SWAPU(ev); \\\n";
@@ -241,6 +243,25 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
   }
   for (int s = 0; s < nslots; ++s)
     if (!sdeg[s]) o << "U |= __builtin_amdgcn_ubfe(S[" << (s >> 5) << "], " << (s & 31) << ", 1) << 31; \\\n";
+  o << "} while (0)\n";
+  // Check state after the first iteration of a first pass with equal priors
+  // lambda > 0 (every q = lambda): alpha*min1 = alpha*lambda, alpha*min2 the
+  // same (or alpha*lsat for a check of degree 1), argmin the first edge, and
+  // every r sign equal to the check's syndrome bit.
+  o << "#define NB_INIT1() do { \\\n";
+  {
+    std::vector<uint32_t> amc(nwc, 0u);
+    for (int s = 0; s < nslots; ++s)
+      if (sdeg[s]) amc[cw[s]] |= 1u << (off[s] + 2 * sdeg[s] - 1);
+    for (int w = 0; w < nwc; ++w) o << "W[" << w << "] = " << amc[w] << "u; \\\n";
+  }
+  for (int s = 0; s < nslots; ++s) {
+    if (!sdeg[s]) continue;
+    const uint32_t mask = ((1u << sdeg[s]) - 1u) << off[s];
+    o << "A1[" << s << "] = A1I; A2[" << s << "] = " << (sdeg[s] >= 2 ? "A1I" : "A2I1") << "; W[" << cw[s]
+      << "] |= (u32)__builtin_amdgcn_sbfe((int)S[" << (s >> 5) << "], " << (s & 31) << ", 1) & " << mask
+      << "u; \\\n";
+  }
   o << "} while (0)\n";
   return o.str();
 }

@@ -241,6 +241,9 @@ struct LaneArgsHost {
   int stop;
   int tie_lowest;
   unsigned long long seed;
+  float a1_init;
+  float a2_init1;
+  int skip0;
 };
 
 bool uniform_prior(const bpdc_code_s* c) {
@@ -294,6 +297,12 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   a.stop = p->kp.stop;
   a.tie_lowest = p->kp.tie_lowest;
   a.seed = p->kp.seed;
+  // equal positive priors below the saturation level: the first iteration's
+  // check state is the same for every shot up to the syndrome signs
+  const float lam0 = c->lam[0];
+  a.skip0 = (uniform_prior(c) && lam0 > 0.0f && lam0 < p->kp.lsat && p->kp.T1 >= 1) ? 1 : 0;
+  a.a1_init = p->kp.alpha * lam0;
+  a.a2_init1 = p->kp.alpha * p->kp.lsat;
   void* args[] = {&a};
   const int64_t want = (io.B + 63) / 64;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cp.lane.grid, want));
