@@ -119,6 +119,12 @@ __device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
   const u32 hi = (w + 1 < NW) ? S[(w + 1 < NW) ? w + 1 : 0] : 0u;
   return sh ? __builtin_amdgcn_alignbit(hi, lo, sh) : lo;
 }
+// x of lane `src` (uniform across the wave) into scalar registers.
+__device__ __forceinline__ long long readlane64(long long x, int src) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)x >> 32), src);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
 }  // namespace bpdc_lane
 
 // Accumulate q into the next state of slot s (bit b): first event / later events.
@@ -183,8 +189,10 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
 #if NB_POSTERIOR
   __shared__ float sLam2[NB_N * NB_LSTR];
 #endif
-  __shared__ int sDptr[NB_MD + 1];
-  __shared__ short sDcol[NB_DNNZ];
+  __shared__ short sDcolP[NB_MD * NB_DMAXROW];  // D rows, padded to the largest degree
+#if !NB_DUNIFORM
+  __shared__ unsigned char sDdeg[NB_MD];
+#endif
   __shared__ u32 sCut[2][NB_RC32];
   __shared__ short sColRow[NB_N];
   __shared__ u32 sSyn[NB_CHUNK][NB_SW32];  // staged syndromes of the reservoir
@@ -195,8 +203,13 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   const int lane = threadIdx.x;
   const bool isB = NB_PAIRED && (lane & 1);
   const int first_of_pair = NB_PAIRED ? (lane & ~1) : lane;
-  for (int i = lane; i <= NB_MD; i += 64) sDptr[i] = a.d_row_ptr[i];
-  for (int i = lane; i < NB_DNNZ; i += 64) sDcol[i] = (short)a.d_col[i];
+  for (int h = lane; h < NB_MD; h += 64) {
+    const int b0 = a.d_row_ptr[h], deg = a.d_row_ptr[h + 1] - b0;
+    for (int k = 0; k < NB_DMAXROW; ++k) sDcolP[h * NB_DMAXROW + k] = (short)(k < deg ? a.d_col[b0 + k] : 0);
+#if !NB_DUNIFORM
+    sDdeg[h] = (unsigned char)deg;
+#endif
+  }
   for (int i = lane; i < NB_N; i += 64) sColRow[i] = nb_col_row[i];
 #if !NB_UNIFORM_PRIOR
   for (int i = lane; i < 2 * NB_ROWS; i += 64)
@@ -341,21 +354,38 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         const int src = __ffsll((long long)dcm) - 1;
         const int ssid = NB_PAIRED ? (src >> 1) : src;
         dcm &= dcm - 1;
-        const long long sshot = __shfl(shot, src);
+        const long long sshot = readlane64(shot, src);
         for (int w = lane; w < 2 * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
-        __syncthreads();
-        for (int h = lane; h < NB_MD; h += 64) {
-          const int b0 = sDptr[h], deg = sDptr[h + 1] - b0;
-          int cols[NB_DMAXROW];
-          float vals[NB_DMAXROW];
-          for (int k = 0; k < deg; ++k) {
-            cols[k] = sDcol[b0 + k];
-            vals[k] = bpdc_dev::sat(sL[cols[k] * NB_LSTR + ssid], LS);
+        // nominees of rows lane, lane + 64, ...: all loads first, then the picks
+        constexpr int kRowIt = (NB_MD + 63) / 64;
+        int pick[kRowIt];
+#pragma unroll
+        for (int it = 0; it < kRowIt; ++it) {
+          const int h = lane + 64 * it;
+          pick[it] = -1;
+          if (h < NB_MD) {
+            int cols[NB_DMAXROW];
+            float vals[NB_DMAXROW];
+#pragma unroll
+            for (int k = 0; k < NB_DMAXROW; ++k) {
+              cols[k] = sDcolP[h * NB_DMAXROW + k];
+              vals[k] = bpdc_dev::sat(sL[cols[k] * NB_LSTR + ssid], LS);
+            }
+#if NB_DUNIFORM
+            const int deg = NB_DMAXROW;
+#else
+            const int deg = sDdeg[h];
+#endif
+            if (deg > 0)
+              pick[it] = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
+                                                       (u64)(a.shot_offset + sshot), (u64)h);
           }
-          if (deg > 0) {
-            const int pick = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
-                                                           (u64)(a.shot_offset + sshot), (u64)h);
-            const int pr = sColRow[pick];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kRowIt; ++it) {
+          if (pick[it] >= 0) {
+            const int pr = sColRow[pick[it]];
             atomicOr(&sCut[pr & 1][(pr >> 1) >> 5], 1u << ((pr >> 1) & 31));
           }
         }
@@ -381,16 +411,20 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         const int src = __ffsll((long long)fm) - 1;
         const int ssid = NB_PAIRED ? (src >> 1) : src;
         fm &= fm - 1;
-        const long long sshot = __shfl(shot, src);
-        const int spass = __shfl(pass, src);
-        const bool sconv = __shfl((int)conv, src) != 0;
-        const int st = __shfl(t, src);
-        const int sit1 = __shfl(it1, src);
+        const long long sshot = readlane64(shot, src);
+        const int spass = __builtin_amdgcn_readlane(pass, src);
+        const bool sconv = __builtin_amdgcn_readlane((int)conv, src) != 0;
+        const int st = __builtin_amdgcn_readlane(t, src);
+        const int sit1 = __builtin_amdgcn_readlane(it1, src);
+        float xs[NB_NW64];
 #pragma unroll
         for (int w = 0; w < NB_NW64; ++w) {
           const int u = w * 64 + lane;
-          float x = 1.0f;
-          if (u < NB_N) x = sL[u * NB_LSTR + ssid];
+          xs[w] = (u < NB_N) ? sL[(u < NB_N ? u : 0) * NB_LSTR + ssid] : 1.0f;
+        }
+#pragma unroll
+        for (int w = 0; w < NB_NW64; ++w) {
+          const float x = xs[w];
           const u64 word = __ballot(x <= 0.0f);
           const u64 cword = __ballot(spass && x == __builtin_huge_valf());
           if (lane == 0) {

@@ -173,13 +173,16 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
   size_t dnnz = 0;
   for (auto& r : g.drows) dnnz += r.size();
 
+  bool uniform_drows = !g.drows.empty();
+  for (auto& r : g.drows) uniform_drows = uniform_drows && (int)r.size() == max_deg(g.drows);
   std::ostringstream o;
   o << "#define NB_M " << m << "\n#define NB_N " << n << "\n#define NB_MD " << md
     << "\n#define NB_SW32 " << (m + 31) / 32 << "\n#define NB_SW64 " << (m + 63) / 64
     << "\n#define NB_NW64 " << (n + 63) / 64 << "\n#define NB_NC32 " << (n + 31) / 32
     << "\n#define NB_SLOTS " << nslots << "\n#define NB_ROWS " << nrows << "\n#define NB_RC32 "
     << (nrows + 31) / 32 << "\n#define NB_NWC " << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1)
-    << "\n#define NB_DMAXROW " << std::max(1, max_deg(g.drows)) << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0)
+    << "\n#define NB_DMAXROW " << std::max(1, max_deg(g.drows)) << "\n#define NB_DUNIFORM " << (uniform_drows ? 1 : 0)
+    << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0)
     << "\n#define NB_PAIRED " << (paired ? 1 : 0) << "\n#define NB_HALFOFF " << (paired ? pr.block / 2 : 0)
     << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0)
     << "\n";
