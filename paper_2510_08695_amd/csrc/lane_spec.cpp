@@ -251,19 +251,23 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
   // lambda > 0 (every q = lambda): alpha*min1 = alpha*lambda, alpha*min2 the
   // same (or alpha*lsat for a check of degree 1), argmin the first edge, and
   // every r sign equal to the check's syndrome bit.
+  // A check of degree >= 2 gets no argmin bit (its two minima are equal, so
+  // every edge reads alpha*min1 and A2 need not be written); a check of
+  // degree 1 marks its only edge, which reads alpha*lsat.
   o << "#define NB_INIT1() do { \\\n";
   {
     std::vector<uint32_t> amc(nwc, 0u);
     for (int s = 0; s < nslots; ++s)
-      if (sdeg[s]) amc[cw[s]] |= 1u << (off[s] + 2 * sdeg[s] - 1);
+      if (sdeg[s] == 1) amc[cw[s]] |= 1u << (off[s] + 1);
     for (int w = 0; w < nwc; ++w) o << "W[" << w << "] = " << amc[w] << "u; \\\n";
   }
   for (int s = 0; s < nslots; ++s) {
     if (!sdeg[s]) continue;
     const uint32_t mask = ((1u << sdeg[s]) - 1u) << off[s];
-    o << "A1[" << s << "] = A1I; A2[" << s << "] = " << (sdeg[s] >= 2 ? "A1I" : "A2I1") << "; W[" << cw[s]
-      << "] |= (u32)__builtin_amdgcn_sbfe((int)S[" << (s >> 5) << "], " << (s & 31) << ", 1) & " << mask
-      << "u; \\\n";
+    o << "A1[" << s << "] = A1I; ";
+    if (sdeg[s] == 1) o << "A2[" << s << "] = A2I1; ";
+    o << "W[" << cw[s] << "] |= (u32)__builtin_amdgcn_sbfe((int)S[" << (s >> 5) << "], " << (s & 31) << ", 1) & "
+      << mask << "u; \\\n";
   }
   o << "} while (0)\n";
   return o.str();
