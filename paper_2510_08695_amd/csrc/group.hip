@@ -6,16 +6,18 @@
 // batch are first grouped by code, largest codes first, so that long shots
 // start early and consecutive shots of a workgroup share the code's index
 // arrays in cache).  Per iteration (flooding schedule, Sec. II.C) it runs
-//   check phase  : one thread per check: q = sat(L_v - r_old) for each edge,
-//                  new (alpha*min1, alpha*min2, argmin, r-sign bits);
 //   variable phase: one thread per column: L_v = prior + sum r (ascending
 //                  check order), +inf on cut columns (Algorithm 2);
-//   stop phase   : one thread per check: parity of [L <= 0] over the check
-//                  against the syndrome bit (H e = s);
-// with a workgroup barrier between phases.  After a failed first pass it runs
-// degeneracy cutting (Sec. III.A) with one thread per row of D and the second
-// pass, then writes the packed correction.  The arithmetic order is that of
-// every other decoder of the library, so results are bit-identical.
+//   check phase  : one thread per check: q = sat(L_v - r_old) for each edge,
+//                  new (alpha*min1, alpha*min2, argmin, r-sign bits), and the
+//                  parity of [L <= 0] over the check against the syndrome bit
+//                  (the stop test H e = s of this iteration);
+// with a workgroup barrier after each.  The code's adjacency is read from
+// padded column-major tables (one coalesced load per edge).  After a failed
+// first pass it runs degeneracy cutting (Sec. III.A) with one thread per row
+// of D and the second pass, then writes the packed correction.  The
+// arithmetic order is that of every other decoder of the library, so results
+// are bit-identical.
 #include "internal.h"
 // after the HIP runtime header: bpdc_device.h itself includes nothing
 #include "bpdc_device.h"
@@ -34,6 +36,9 @@ struct GCode {
   const int32_t* d_row_ptr;
   const int32_t* d_col;
   const float* lam;
+  const int32_t* v_ell;  // [max_col_deg][n]: (check << 5) | position in the check's row, ascending checks; -1 pad
+  const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; -1 pad
+  int max_col_deg, max_row_deg;
 };
 
 namespace {
@@ -85,7 +90,7 @@ template <class InfoT>
 __global__ void __launch_bounds__(1024) k_group(GArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long sIdx;
-  __shared__ int sUnsat;
+  __shared__ int sUnsat[2];  // stop-test flag, by iteration parity (read and reset with no barrier between)
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const KParams& P = a.p;
@@ -138,43 +143,33 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           if (use_lam2) Lv = lam2[v];
           else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
           if (Lv != INF) {
-            for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) {
-              const int e = C.h_col_edge[k];
-              const int c = C.h_edge_row[e];
-              Lv = Lv + decode_r<InfoT>(A1[c], A2[c], info[c], e - C.h_row_ptr[c]);
+            for (int k = 0; k < C.max_col_deg; ++k) {
+              const int ent = C.v_ell[(size_t)k * n + v];
+              if (ent < 0) break;
+              const int c = ent >> 5;
+              Lv = Lv + decode_r<InfoT>(A1[c], A2[c], info[c], ent & 31);
             }
           }
           L[v] = Lv;
         }
-        if (tid == 0) sUnsat = 0;
+        if (tid == 0) sUnsat[t & 1] = 0;
         __syncthreads();
-        if (t >= 1) {
-          // ---- stop phase: H e = s with e = [L <= 0] ----
-          int bad = 0;
-          for (int c = tid; c < m; c += nt) {
-            u32 par = (synw[c >> 5] >> (c & 31)) & 1u;
-            for (int e = C.h_row_ptr[c]; e < C.h_row_ptr[c + 1]; ++e) par ^= (L[C.h_col[e]] <= 0.0f) ? 1u : 0u;
-            bad |= (int)par;
-          }
-          if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat, 1);
-          __syncthreads();
-          const bool ok = sUnsat == 0;
-          if ((P.stop && ok) || t >= T) {
-            conv = ok;
-            it[pass] = t;
-            break;
-          }
-        }
-        // ---- check phase: next check state from q = sat(L - r_old) ----
+        // ---- check phase: next check state from q = sat(L - r_old), with the stop
+        // test H e = s (e = [L <= 0]) on the way; the new state is not used
+        // when the pass ends here ----
+        int bad = 0;
         for (int c = tid; c < m; c += nt) {
-          const int e0 = C.h_row_ptr[c], d = C.h_row_ptr[c + 1] - e0;
           const float a1o = A1[c], a2o = A2[c];
           const InfoT io = info[c];
           float m1 = LS, m2 = LS;
-          int amin = 0;
-          u32 sb = 0;
-          for (int k = 0; k < d; ++k) {
-            const float q = bpdc_dev::sat(L[C.h_col[e0 + k]] - decode_r<InfoT>(a1o, a2o, io, k), LS);
+          int amin = 0, d = 0;
+          u32 sb = 0, par = (synw[c >> 5] >> (c & 31)) & 1u;
+          for (int k = 0; k < C.max_row_deg; ++k) {
+            const int v = C.c_ell[(size_t)k * m + c];
+            if (v < 0) break;
+            const float Lv = L[v];
+            par ^= (Lv <= 0.0f) ? 1u : 0u;
+            const float q = bpdc_dev::sat(Lv - decode_r<InfoT>(a1o, a2o, io, k), LS);
             const float aq = fabsf(q);
             if (aq < m1) {
               m2 = m1;
@@ -184,14 +179,25 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
               m2 = aq;
             }
             sb |= ((q < 0.0f) ? 1u : 0u) << k;
+            d = k + 1;
           }
-          const u32 par = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
-          const u32 rb = par ? (sb ^ ((1u << d) - 1u)) : sb;
+          bad |= (int)par;
+          const u32 rp = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
+          const u32 rb = rp ? (sb ^ ((1u << d) - 1u)) : sb;
           A1[c] = P.alpha * m1;
           A2[c] = P.alpha * m2;
           info[c] = (InfoT)(rb | ((u32)amin << InfoTraits<InfoT>::kPosShift));
         }
+        if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
         __syncthreads();
+        if (t >= 1) {
+          const bool ok = sUnsat[t & 1] == 0;
+          if ((P.stop && ok) || t >= T) {
+            conv = ok;
+            it[pass] = t;
+            break;
+          }
+        }
         ++t;
       }
       if (pass == 1 || conv) break;

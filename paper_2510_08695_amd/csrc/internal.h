@@ -25,6 +25,8 @@ struct DevCode {
   int32_t* d_row_ptr = nullptr;  // [md+1]
   int32_t* d_col = nullptr;      // [dnnz]
   float* lam = nullptr;          // [n]
+  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 5 | position in row), ascending rows; -1 pad
+  int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; -1 pad
 };
 
 // Runtime decoder parameters as the kernels see them.
@@ -87,6 +89,9 @@ struct GCodeHost {
   const int32_t* d_row_ptr;
   const int32_t* d_col;
   const float* lam;
+  const int32_t* v_ell;
+  const int32_t* c_ell;
+  int max_col_deg, max_row_deg;
 };
 
 // Weighted min-sum forward (checkpointed) and adjoint (wms.hip).

@@ -447,7 +447,7 @@ bpdc_status build_code_table(bpdc_plan_s* p) {
   for (size_t i = 0; i < p->codes.size(); ++i) {
     const bpdc::DevCode& d = p->codes[i]->dev;
     tab[i] = {d.n, d.m, d.md, p->kp.second_pass_posterior, d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge,
-              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam};
+              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam, d.v_ell, d.c_ell, d.max_col_deg, d.max_row_deg};
     rank[i] = (int32_t)i;
   }
   std::stable_sort(rank.begin(), rank.end(),
@@ -556,12 +556,22 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
     }
   }
   std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
+  // padded column-major adjacency for the group kernel (one coalesced load per edge)
+  std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, -1), cell((size_t)std::max(1, d.max_row_deg) * g.m, -1);
+  for (int v = 0; v < g.n; ++v)
+    for (int k = cp[v]; k < cp[v + 1]; ++k) {
+      const int edge = ce[k], r = er[edge];
+      vell[(size_t)(k - cp[v]) * g.n + v] = (r << 5) | (edge - hrp[r]);
+    }
+  for (int r = 0; r < g.m; ++r)
+    for (int k = hrp[r]; k < hrp[r + 1]; ++k) cell[(size_t)(k - hrp[r]) * g.m + r] = hci[k];
   if (hipGetDevice(&c->device) != hipSuccess) return fail(BPDC_ERR_HIP, "no HIP device");
   hipError_t e;
   if ((e = upload(&d.h_row_ptr, hrp)) != hipSuccess || (e = upload(&d.h_col, hci)) != hipSuccess ||
       (e = upload(&d.h_col_ptr, cp)) != hipSuccess || (e = upload(&d.h_col_edge, ce)) != hipSuccess ||
       (e = upload(&d.h_edge_row, er)) != hipSuccess || (e = upload(&d.d_row_ptr, drp)) != hipSuccess ||
-      (e = upload(&d.d_col, dci)) != hipSuccess || (e = upload(&d.lam, c->lam)) != hipSuccess) {
+      (e = upload(&d.d_col, dci)) != hipSuccess || (e = upload(&d.lam, c->lam)) != hipSuccess ||
+      (e = upload(&d.v_ell, vell)) != hipSuccess || (e = upload(&d.c_ell, cell)) != hipSuccess) {
     bpdc_code_destroy(c.release());
     return fail(e == hipErrorOutOfMemory ? BPDC_ERR_OOM : BPDC_ERR_HIP, "upload: %s", hipGetErrorString(e));
   }
@@ -572,7 +582,8 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
 bpdc_status bpdc_code_destroy(bpdc_code c) {
   if (!c) return BPDC_OK;
   bpdc::DevCode& d = c->dev;
-  void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row, d.d_row_ptr, d.d_col, d.lam};
+  void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row,
+                  d.d_row_ptr, d.d_col,     d.lam,       d.v_ell,      d.c_ell};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
