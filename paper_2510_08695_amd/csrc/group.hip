@@ -143,11 +143,24 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           if (use_lam2) Lv = lam2[v];
           else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
           if (Lv != INF) {
-            for (int k = 0; k < C.max_col_deg; ++k) {
-              const int ent = C.v_ell[(size_t)k * n + v];
-              if (ent < 0) break;
-              const int c = ent >> 5;
-              Lv = Lv + decode_r<InfoT>(A1[c], A2[c], info[c], ent & 31);
+            // entries in chunks of 4, all loads of a chunk issued before the sums
+            for (int k0 = 0; k0 < C.max_col_deg; k0 += 4) {
+              int ent[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? C.v_ell[(size_t)(k0 + j) * n + v] : -1;
+              float a1[4], a2[4];
+              InfoT in[4];
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                const int c = ent[j] >= 0 ? (ent[j] >> 5) : 0;
+                a1[j] = A1[c];
+                a2[j] = A2[c];
+                in[j] = info[c];
+              }
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (ent[j] >= 0) Lv = Lv + decode_r<InfoT>(a1[j], a2[j], in[j], ent[j] & 31);
+              if (ent[3] < 0) break;
             }
           }
           L[v] = Lv;
@@ -164,22 +177,33 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           float m1 = LS, m2 = LS;
           int amin = 0, d = 0;
           u32 sb = 0, par = (synw[c >> 5] >> (c & 31)) & 1u;
-          for (int k = 0; k < C.max_row_deg; ++k) {
-            const int v = C.c_ell[(size_t)k * m + c];
-            if (v < 0) break;
-            const float Lv = L[v];
-            par ^= (Lv <= 0.0f) ? 1u : 0u;
-            const float q = bpdc_dev::sat(Lv - decode_r<InfoT>(a1o, a2o, io, k), LS);
-            const float aq = fabsf(q);
-            if (aq < m1) {
-              m2 = m1;
-              m1 = aq;
-              amin = k;
-            } else if (aq < m2) {
-              m2 = aq;
+          // columns in chunks of 8, all loads of a chunk issued before the updates
+          for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
+            int vv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? C.c_ell[(size_t)(k0 + j) * m + c] : -1;
+            float Lj[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Lj[j] = L[vv[j] >= 0 ? vv[j] : 0];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (vv[j] < 0) break;
+              const int k = k0 + j;
+              const float Lv = Lj[j];
+              par ^= (Lv <= 0.0f) ? 1u : 0u;
+              const float q = bpdc_dev::sat(Lv - decode_r<InfoT>(a1o, a2o, io, k), LS);
+              const float aq = fabsf(q);
+              if (aq < m1) {
+                m2 = m1;
+                m1 = aq;
+                amin = k;
+              } else if (aq < m2) {
+                m2 = aq;
+              }
+              sb |= ((q < 0.0f) ? 1u : 0u) << k;
+              d = k + 1;
             }
-            sb |= ((q < 0.0f) ? 1u : 0u) << k;
-            d = k + 1;
+            if (vv[7] < 0) break;
           }
           bad |= (int)par;
           const u32 rp = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
