@@ -109,10 +109,9 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     const int n = C.n, m = C.m;
     const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
     // LDS carve for this code
-    float* L = (float*)smem;                       // [n]
-    float* A1 = L + n;                             // [m]
-    float* A2 = A1 + m;                            // [m]
-    u32* cutw = (u32*)(A2 + m);                    // [ceil(n/32)]
+    float2* A12 = (float2*)smem;                   // [m] (alpha*min1, alpha*min2) per check
+    float* L = (float*)(A12 + m);                  // [n]
+    u32* cutw = (u32*)(L + n);                     // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     float* lam2 = (float*)(synw + ((m + 31) >> 5));  // [n] (posterior second pass)
     InfoT* info = (InfoT*)(lam2 + (P.second_pass_posterior ? n : 0));  // [m]
@@ -130,8 +129,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
       const int T = pass ? P.T2 : P.T1;
       const bool use_lam2 = pass == 1 && P.second_pass_posterior;
       for (int c = tid; c < m; c += nt) {
-        A1[c] = 0.0f;
-        A2[c] = 0.0f;
+        A12[c] = make_float2(0.0f, 0.0f);
         info[c] = (InfoT)0;
       }
       __syncthreads();
@@ -153,8 +151,9 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
                 const int c = ent[j] >= 0 ? (ent[j] >> 5) : 0;
-                a1[j] = A1[c];
-                a2[j] = A2[c];
+                const float2 aa = A12[c];
+                a1[j] = aa.x;
+                a2[j] = aa.y;
                 in[j] = info[c];
               }
 #pragma unroll
@@ -172,7 +171,8 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
         // when the pass ends here ----
         int bad = 0;
         for (int c = tid; c < m; c += nt) {
-          const float a1o = A1[c], a2o = A2[c];
+          const float2 aa = A12[c];
+          const float a1o = aa.x, a2o = aa.y;
           const InfoT io = info[c];
           float m1 = LS, m2 = LS;
           int amin = 0, d = 0;
@@ -208,8 +208,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           bad |= (int)par;
           const u32 rp = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
           const u32 rb = rp ? (sb ^ ((1u << d) - 1u)) : sb;
-          A1[c] = P.alpha * m1;
-          A2[c] = P.alpha * m2;
+          A12[c] = make_float2(P.alpha * m1, P.alpha * m2);
           info[c] = (InfoT)(rb | ((u32)amin << InfoTraits<InfoT>::kPosShift));
         }
         if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
