@@ -70,20 +70,24 @@ struct InfoTraits;
 template <>
 struct InfoTraits<uint16_t> {
   static constexpr int kPosShift = 12;
-  static constexpr u32 kSignMask = 0xFFFu;
 };
 template <>
 struct InfoTraits<u32> {
   static constexpr int kPosShift = 27;
-  static constexpr u32 kSignMask = 0x7FFFFFFu;
 };
 
+// r of the edge at row position k from the packed check state: alpha*min2 on
+// the argmin edge, alpha*min1 elsewhere, sign bit k of the info word.
 template <class InfoT>
-__device__ __forceinline__ float decode_r(float a1, float a2, InfoT info, int k) {
-  const u32 w = (u32)info;
-  const int amin = (int)(w >> InfoTraits<InfoT>::kPosShift);
-  const float mag = (amin == k) ? a2 : a1;
-  return ((w >> k) & 1u) ? -mag : mag;
+__device__ __forceinline__ float decode_r2(float2 a12, u32 info, int k) {
+  const float mag = ((int)(info >> InfoTraits<InfoT>::kPosShift) == k) ? a12.y : a12.x;
+  return __uint_as_float(__float_as_uint(mag) ^ (((info >> k) & 1u) << 31));
+}
+
+// Load through a global-address-space pointer (the code tables are reached
+// through a table in device memory, so the compiler cannot infer it).
+__device__ __forceinline__ int gload(const int32_t* p, int i) {
+  return ((const __attribute__((address_space(1))) int32_t*)p)[i];
 }
 
 template <class InfoT>
@@ -141,24 +145,26 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           if (use_lam2) Lv = lam2[v];
           else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
           if (Lv != INF) {
-            // entries in chunks of 4, all loads of a chunk issued before the sums
+            // entries in chunks of 4, all loads of a chunk issued before the sums;
+            // padding entries (-1) read check 0 and add nothing
             for (int k0 = 0; k0 < C.max_col_deg; k0 += 4) {
               int ent[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? C.v_ell[(size_t)(k0 + j) * n + v] : -1;
-              float a1[4], a2[4];
-              InfoT in[4];
+              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : -1;
+              float2 aa[4];
+              u32 in[4];
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
-                const int c = ent[j] >= 0 ? (ent[j] >> 5) : 0;
-                const float2 aa = A12[c];
-                a1[j] = aa.x;
-                a2[j] = aa.y;
-                in[j] = info[c];
+                const int c = (ent[j] >= 0 ? ent[j] : 0) >> 5;
+                aa[j] = A12[c];
+                in[j] = (u32)info[c];
               }
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
-                if (ent[j] >= 0) Lv = Lv + decode_r<InfoT>(a1[j], a2[j], in[j], ent[j] & 31);
+              for (int j = 0; j < 4; ++j) {
+                const float r = decode_r2<InfoT>(aa[j], in[j], ent[j] & 31);
+                const float s = Lv + r;
+                Lv = (ent[j] >= 0) ? s : Lv;
+              }
               if (ent[3] < 0) break;
             }
           }
@@ -171,37 +177,33 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
         // when the pass ends here ----
         int bad = 0;
         for (int c = tid; c < m; c += nt) {
-          const float2 aa = A12[c];
-          const float a1o = aa.x, a2o = aa.y;
-          const InfoT io = info[c];
+          const float2 ao = A12[c];
+          const u32 io = (u32)info[c];
           float m1 = LS, m2 = LS;
           int amin = 0, d = 0;
           u32 sb = 0, par = (synw[c >> 5] >> (c & 31)) & 1u;
-          // columns in chunks of 8, all loads of a chunk issued before the updates
+          // columns in chunks of 8, all loads of a chunk issued before the
+          // updates; padding entries (-1) contribute nothing
           for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
             int vv[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? C.c_ell[(size_t)(k0 + j) * m + c] : -1;
+            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? gload(C.c_ell, (k0 + j) * m + c) : -1;
             float Lj[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) Lj[j] = L[vv[j] >= 0 ? vv[j] : 0];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-              if (vv[j] < 0) break;
+              const bool ok = vv[j] >= 0;
               const int k = k0 + j;
               const float Lv = Lj[j];
-              par ^= (Lv <= 0.0f) ? 1u : 0u;
-              const float q = bpdc_dev::sat(Lv - decode_r<InfoT>(a1o, a2o, io, k), LS);
-              const float aq = fabsf(q);
-              if (aq < m1) {
-                m2 = m1;
-                m1 = aq;
-                amin = k;
-              } else if (aq < m2) {
-                m2 = aq;
-              }
-              sb |= ((q < 0.0f) ? 1u : 0u) << k;
-              d = k + 1;
+              par ^= (ok && Lv <= 0.0f) ? 1u : 0u;
+              const float q = bpdc_dev::sat(Lv - decode_r2<InfoT>(ao, io, k), LS);
+              const float aq = ok ? fabsf(q) : INF;
+              amin = (aq < m1) ? k : amin;
+              m2 = __builtin_amdgcn_fmed3f(aq, m1, m2);
+              m1 = fminf(aq, m1);
+              sb |= ((ok && q < 0.0f) ? 1u : 0u) << k;
+              d = ok ? k + 1 : d;
             }
             if (vv[7] < 0) break;
           }
