@@ -14,10 +14,10 @@
 //   per column ("row") i : the cut bit C[], and the posterior L written to
 //                 LDS (sL, [row][65 lanes]) every sweep for DC and output.
 //
-// In the paired layout two adjacent lanes share a shot: lane A holds checks
-// 0..m/2-1 and a set of columns, lane B the images of both under an
-// automorphism of the code, and the edges that cross between the halves are
-// exchanged with DPP lane swaps (see lane_spec.cpp).
+// A shot is decoded by a group of NB_G adjacent lanes (1, 2 or 4): lane k of
+// the group holds the images under an automorphism of the code of lane 0's
+// checks and columns, and the edges that cross between lanes are exchanged
+// with DPP quad permutations (see lane_spec.cpp).
 //
 // One sweep visits every row once: L = lambda + sum of r (ascending check
 // order), the hard decision and the stop-test parity of each check (H e = s,
@@ -37,7 +37,7 @@
 // all its lanes are idle.
 
 struct LaneArgs {
-  const unsigned long long* syn;  // [B][NB_SW64]
+  const unsigned* synp;           // [B][NB_G][NB_SPW] syndrome bits of each lane's slots (bpdc_lane_prepare)
   long long B;
   long long shot_offset;
   unsigned long long* corr;       // [B][NB_NW64]
@@ -63,11 +63,11 @@ struct LaneArgs {
   int skip0;                      // start first passes from that state (equal priors, 0 < lambda < lsat)
 };
 
-// Posteriors in LDS as [column][shot slot of the wave]: one slot per lane, or
-// per pair of lanes in the paired layout (lane B's columns are lane A's
-// shifted by NB_HALFOFF, so both lanes store with the same offsets).  The
-// strides 65 and 33 keep column-wise reads free of bank conflicts.
-#define NB_LSTR (NB_PAIRED ? 33 : 65)
+// Posteriors in LDS as [column][shot slot of the wave], one slot per lane
+// group (lane k's columns are lane 0's shifted by NB_LOFFk, so all lanes of a
+// group store with the same offsets).  The odd strides keep column-wise reads
+// free of bank conflicts.
+#define NB_LSTR (64 / NB_G + 1)
 #define NB_CHUNK 32   // largest number of shots a wave claims at once
 
 namespace bpdc_lane {
@@ -105,20 +105,18 @@ __device__ __forceinline__ float cutsel(float L, u32 cw, const int b, u32 infbit
   return __uint_as_float(bfi(mask, infbits, __float_as_uint(L)));
 }
 
-// Exchange with the adjacent lane (lanes 2i <-> 2i+1): one DPP move.
-__device__ __forceinline__ u32 swapu(u32 x) {
-  return (u32)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+// Exchange with lane (lane xor J) of the same group of four: one DPP quad
+// permutation (quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]).
+template <int J>
+__device__ __forceinline__ u32 xchgu(u32 x) {
+  constexpr int ctrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x1B);
+  return (u32)__builtin_amdgcn_mov_dpp((int)x, ctrl, 0xF, 0xF, false);
 }
-__device__ __forceinline__ float swapf(float x) { return __uint_as_float(swapu(__float_as_uint(x))); }
+template <int J>
+__device__ __forceinline__ float xchgf(float x) {
+  return __uint_as_float(xchgu<J>(__float_as_uint(x)));
+}
 
-// Bits [start, start + 32) of the little-endian bit vector S (zero beyond).
-template <int NW>
-__device__ __forceinline__ u32 bits32(const u32 (&S)[NW], const int start) {
-  const int w = start >> 5, sh = start & 31;
-  const u32 lo = (w < NW) ? S[(w < NW) ? w : 0] : 0u;
-  const u32 hi = (w + 1 < NW) ? S[(w + 1 < NW) ? w + 1 : 0] : 0u;
-  return sh ? __builtin_amdgcn_alignbit(hi, lo, sh) : lo;
-}
 // x of lane `src` (uniform across the wave) into scalar registers.
 __device__ __forceinline__ long long readlane64(long long x, int src) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, src);
@@ -168,9 +166,15 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 // that start at lsat, and clamping changes neither (|q| >= lsat leaves every
 // minimum, argmin and second minimum as they are; the sign is kept).
 #define NB_Q(L, r) ((L) - (r))
-#define NB_SWAPF(x) bpdc_lane::swapf(x)
-#define NB_SWAPU(x) bpdc_lane::swapu(x)
-#define NB_PICK(a, b) (isB ? (b) : (a))
+#define NB_XF0(x) (x)
+#define NB_XF1(x) bpdc_lane::xchgf<1>(x)
+#define NB_XF2(x) bpdc_lane::xchgf<2>(x)
+#define NB_XF3(x) bpdc_lane::xchgf<3>(x)
+#define NB_XU1(x) bpdc_lane::xchgu<1>(x)
+#define NB_XU2(x) bpdc_lane::xchgu<2>(x)
+#define NB_XU3(x) bpdc_lane::xchgu<3>(x)
+// true on the lanes of a group whose index is in the bit mask
+#define NB_IN(mask) ((((mask) >> role) & 1) != 0)
 
 #if NB_UNIFORM_PRIOR
 #define NB_LAM1(i) LAMU
@@ -193,16 +197,16 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
 #if !NB_DUNIFORM
   __shared__ unsigned char sDdeg[NB_MD];
 #endif
-  __shared__ u32 sCut[2][NB_RC32];
+  __shared__ u32 sCut[NB_G][NB_RC32];
   __shared__ short sColRow[NB_N];
-  __shared__ u32 sSyn[NB_CHUNK][NB_SW32];  // staged syndromes of the reservoir
+  __shared__ u32 sSyn[NB_CHUNK][NB_G * NB_SPW];  // staged syndrome words of the reservoir
 #if !NB_UNIFORM_PRIOR
-  __shared__ float sLamRow[2][NB_ROWS];
+  __shared__ float sLamRow[NB_G][NB_ROWS];
 #endif
 
   const int lane = threadIdx.x;
-  const bool isB = NB_PAIRED && (lane & 1);
-  const int first_of_pair = NB_PAIRED ? (lane & ~1) : lane;
+  const int role = lane & (NB_G - 1);  // this lane's index in its shot's group
+  const int first = lane & ~(NB_G - 1);
   for (int h = lane; h < NB_MD; h += 64) {
     const int b0 = a.d_row_ptr[h], deg = a.d_row_ptr[h + 1] - b0;
     for (int k = 0; k < NB_DMAXROW; ++k) sDcolP[h * NB_DMAXROW + k] = (short)(k < deg ? a.d_col[b0 + k] : 0);
@@ -212,15 +216,16 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   }
   for (int i = lane; i < NB_N; i += 64) sColRow[i] = nb_col_row[i];
 #if !NB_UNIFORM_PRIOR
-  for (int i = lane; i < 2 * NB_ROWS; i += 64)
+  for (int i = lane; i < NB_G * NB_ROWS; i += 64)
     sLamRow[i / NB_ROWS][i % NB_ROWS] = a.lam[nb_row_col[i / NB_ROWS][i % NB_ROWS]];
 #endif
   __syncthreads();
 
-  const int sid = NB_PAIRED ? (lane >> 1) : lane;  // this lane's shot slot in sL
-  float* myL = sL + sid + (isB ? NB_HALFOFF * NB_LSTR : 0);
+  const int sid = lane / NB_G;  // this lane's shot slot in sL
+  const int loff = role == 1 ? NB_LOFF1 : (role == 2 ? NB_LOFF2 : (role == 3 ? NB_LOFF3 : 0));
+  float* myL = sL + sid + loff * NB_LSTR;
 #if NB_POSTERIOR
-  float* myLam2 = sLam2 + sid + (isB ? NB_HALFOFF * NB_LSTR : 0);
+  float* myLam2 = sLam2 + sid + loff * NB_LSTR;
 #endif
   const float LS = a.lsat;
   const float alpha = a.alpha;
@@ -228,11 +233,11 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
   const float A1I = a.a1_init, A2I1 = a.a2_init1;
   const u32 SIGNMASK = 0x80000000u, INFBITS = 0x7F800000u;
   // lanes below the first lane of this lane's pair (for numbering new shots)
-  const u64 below = (first_of_pair == 0) ? 0ull : (~0ull >> (64 - first_of_pair));
-  const u64 leaders = NB_PAIRED ? 0x5555555555555555ull : ~0ull;
+  const u64 below = (first == 0) ? 0ull : (~0ull >> (64 - first));
+  const u64 leaders = NB_G == 4 ? 0x1111111111111111ull : (NB_G == 2 ? 0x5555555555555555ull : ~0ull);
 
   float A1[NB_SLOTS], A2[NB_SLOTS];
-  u32 W[NB_NWC], S[NB_SW32], C[NB_RC32];
+  u32 W[NB_NWC], S[NB_SPW], C[NB_RC32];
   long long shot = -1;
   int t = 0, pass = 0, it1 = 0;
   bool want = true, dead = false;
@@ -274,32 +279,19 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         }
         rlo = b0;
         rhi = b0 + c < a.B ? b0 + c : a.B;
-        if (lane < rhi - rlo) {
-          const unsigned long long* sp = a.syn + (rlo + lane) * NB_SW64;
-#pragma unroll
-          for (int w = 0; w < NB_SW32; ++w) {
-            const unsigned long long x = sp[w >> 1];
-            sSyn[lane][w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
-          }
-        }
+        for (int i = lane; i < (rhi - rlo) * (NB_G * NB_SPW); i += 64)
+          sSyn[i / (NB_G * NB_SPW)][i % (NB_G * NB_SPW)] = a.synp[rlo * (NB_G * NB_SPW) + i];
         __syncthreads();
         sbase = rlo;
       }
       const long long avail = rhi - rlo;
-      if ((need >> first_of_pair) & 1ull) {
+      if ((need >> first) & 1ull) {
         const long long rank = __popcll(need & below);
         if (rank < avail) {
           const long long my = rlo + rank;
           shot = my;
-          u32 Sf[NB_SW32];
 #pragma unroll
-          for (int w = 0; w < NB_SW32; ++w) Sf[w] = sSyn[my - sbase][w];
-#pragma unroll
-          for (int w = 0; w < NB_SW32; ++w) {
-            // lane B holds checks m/2.. : its syndrome bits start at m/2
-            const u32 sb = NB_PAIRED ? bits32<NB_SW32>(Sf, (NB_M / 2) + 32 * w) : Sf[w];
-            S[w] = isB ? sb : Sf[w];
-          }
+          for (int w = 0; w < NB_SPW; ++w) S[w] = sSyn[my - sbase][role * NB_SPW + w];
 #pragma unroll
           for (int w = 0; w < NB_RC32; ++w) C[w] = 0u;
 #if NB_UNIFORM_PRIOR
@@ -333,12 +325,15 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
     // constant, so that they are not hoisted out of the loop into registers
     int zoff;
     asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
-    const float* lamrow = &sLamRow[isB ? 1 : 0][0] + zoff;
+    const float* lamrow = &sLamRow[role][0] + zoff;
 #endif
     u32 U = 0u;
     NB_SWEEP();
-#if NB_PAIRED
-    U |= NB_SWAPU(U);
+#if NB_G >= 2
+    U |= NB_XU1(U);
+#endif
+#if NB_G == 4
+    U |= NB_XU2(U);
 #endif
 
     const bool conv = (U >> 31) == 0u;
@@ -352,10 +347,10 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
       u64 dcm = __ballot(to_dc) & leaders;
       while (dcm) {
         const int src = __ffsll((long long)dcm) - 1;
-        const int ssid = NB_PAIRED ? (src >> 1) : src;
+        const int ssid = src / NB_G;
         dcm &= dcm - 1;
         const long long sshot = readlane64(shot, src);
-        for (int w = lane; w < 2 * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
+        for (int w = lane; w < NB_G * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
         // nominees of rows lane, lane + 64, ...: all loads first, then the picks
         constexpr int kRowIt = (NB_MD + 63) / 64;
         int pick[kRowIt];
@@ -386,22 +381,22 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
         for (int it = 0; it < kRowIt; ++it) {
           if (pick[it] >= 0) {
             const int pr = sColRow[pick[it]];
-            atomicOr(&sCut[pr & 1][(pr >> 1) >> 5], 1u << ((pr >> 1) & 31));
+            atomicOr(&sCut[pr & 3][(pr >> 2) >> 5], 1u << ((pr >> 2) & 31));
           }
         }
         __syncthreads();
 #if NB_POSTERIOR
         for (int u = lane; u < NB_N; u += 64) {
           const int cr = sColRow[u];
-          const int r = cr >> 1, hb = cr & 1;
+          const int r = cr >> 2, hb = cr & 3;
           const bool cv = (sCut[hb][r >> 5] >> (r & 31)) & 1u;
           const float x = sL[u * NB_LSTR + ssid];
           sLam2[u * NB_LSTR + ssid] = cv ? __builtin_huge_valf() : bpdc_dev::sat(x, LS);
         }
 #endif
-        if (lane == src || (NB_PAIRED && lane == src + 1)) {
+        if (first == src) {
 #pragma unroll
-          for (int w = 0; w < NB_RC32; ++w) C[w] = sCut[isB ? 1 : 0][w];
+          for (int w = 0; w < NB_RC32; ++w) C[w] = sCut[role][w];
         }
         __syncthreads();
       }
@@ -409,7 +404,7 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
       u64 fm = __ballot(finish) & leaders;
       while (fm) {
         const int src = __ffsll((long long)fm) - 1;
-        const int ssid = NB_PAIRED ? (src >> 1) : src;
+        const int ssid = src / NB_G;
         fm &= fm - 1;
         const long long sshot = readlane64(shot, src);
         const int spass = __builtin_amdgcn_readlane(pass, src);
@@ -462,4 +457,23 @@ extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a)
     }
     t += 1;
   }
+}
+
+// Syndrome words of every shot in the order the lane kernel reads them
+// (NB_PREP): [B][NB_G][NB_SPW], one thread per shot.
+extern "C" __global__ void __launch_bounds__(256) bpdc_lane_prepare(const unsigned long long* syn, long long B,
+                                                                    unsigned* synp) {
+  const long long b = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  unsigned s32[2 * NB_SW64];
+#pragma unroll
+  for (int x = 0; x < NB_SW64; ++x) {
+    const unsigned long long v = syn[b * NB_SW64 + x];
+    s32[2 * x] = (unsigned)v;
+    s32[2 * x + 1] = (unsigned)(v >> 32);
+  }
+  unsigned out[NB_G * NB_SPW];
+  NB_PREP(s32, out);
+#pragma unroll
+  for (int x = 0; x < NB_G * NB_SPW; ++x) synp[b * (NB_G * NB_SPW) + x] = out[x];
 }

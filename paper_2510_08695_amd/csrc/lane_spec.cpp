@@ -1,25 +1,26 @@
 // Generator of the code-specialised part of the lane kernel: for one Tanner
-// graph H and degeneracy matrix D it writes the sizes and the straight-line
-// sweep (see lane_kernel.hip) with every index a literal.
+// graph H and degeneracy matrix D it writes the sizes, lookup tables and the
+// straight-line sweep (see lane_kernel.hip) with every index a literal.
 //
-// Two layouts:
-//  * single: one lane decodes one shot and holds the state of every check;
-//  * paired: two adjacent lanes decode one shot.  This needs an automorphism
-//    sigma of H that is an involution without fixed points, shifting the
-//    checks cyclically by m/2 and the columns by half a block (the
-//    translations of bivariate bicycle and toric codes are of this kind).
-//    Lane A of a pair handles the columns of a set V_A with one column of
-//    every orbit {v, sigma v} and the checks 0..m/2-1; lane B executes the
-//    same instructions on sigma of them.  An edge whose check belongs to the
-//    partner is exchanged with one DPP lane swap per value.  Each lane then
-//    holds half the state, which keeps the kernel inside the VGPR file.
+// Lane groups.  A shot is decoded by a group of 1, 2 or 4 adjacent lanes.
+// With more than one lane this needs a group of automorphisms of H acting
+// freely on columns and checks (lane_spec.h): columns and checks fall into
+// orbits, lane 0 holds one column of every column orbit ("rows") and one check
+// of every check orbit ("slots"), and lane k executes the same instructions on
+// the images under group element k.  An edge from lane 0's column to a check
+// held by lane j (its relative element) is, on lane k, an edge to a check held
+// by lane k xor j, so every lane fetches the check-to-variable message from,
+// and returns the variable-to-check message to, lane k xor j: one DPP quad
+// permutation per value.  Each lane holds 1/|group| of the state.
 //
-// The sweep visits the columns in an order chosen greedily to keep few
-// checks "open" (some but not all of their edges visited) at any time,
-// because every open check holds five accumulator registers.  The order only
-// affects register pressure: a check's minima, argmin and sign parity do not
-// depend on the order of its edges (ties of |q| give equal magnitudes), and
-// each column still adds its incoming messages in ascending check order.
+// The sweep visits the rows in an order chosen greedily to keep few checks
+// "open" (some but not all of their edges visited), because every open check
+// holds five accumulator registers.  The order only affects register
+// pressure: a check's minima, argmin and sign parity do not depend on the
+// order of its edges (ties of |q| give equal magnitudes).  Each lane adds the
+// incoming messages of its column in ascending order of its own check
+// indices; where that differs from the instruction order, the addition picks
+// its operand by the lane's index in the group.
 #include "lane_spec.h"
 
 #include <algorithm>
@@ -68,83 +69,152 @@ int max_deg(const std::vector<std::vector<int>>& a) {
   return d;
 }
 
-}  // namespace
-
-bool find_pairing(const HostGraph& g, Pairing* out) {
-  const int n = g.n, m = g.m;
-  if (n % 2 || m % 2) return false;
-  std::map<std::vector<int>, int> row_of;
-  for (int c = 0; c < m; ++c) {
-    if (g.rows[c].empty()) return false;
-    row_of[g.rows[c]] = c;
+// Check permutation induced by the column permutation sv (rows matched as
+// sets), or false if sv is not an automorphism of H.
+bool induced_checks(const HostGraph& g, const std::map<std::vector<int>, int>& row_of, const std::vector<int>& sv,
+                    std::vector<int>* sc) {
+  sc->assign(g.m, -1);
+  for (int c = 0; c < g.m; ++c) {
+    std::vector<int> img;
+    img.reserve(g.rows[c].size());
+    for (int v : g.rows[c]) img.push_back(sv[v]);
+    std::sort(img.begin(), img.end());
+    auto it = row_of.find(img);
+    if (it == row_of.end()) return false;
+    (*sc)[c] = it->second;
   }
-  if ((int)row_of.size() != m) return false;  // repeated rows: ambiguous
-  for (int B = n; B >= 2; --B) {
-    if (n % B || B % 2) continue;
-    std::vector<int> sv(n);
-    for (int v = 0; v < n; ++v) sv[v] = (v / B) * B + ((v % B) + B / 2) % B;
-    bool ok = true;
-    for (int c = 0; c < m && ok; ++c) {
-      std::vector<int> img;
-      for (int v : g.rows[c]) img.push_back(sv[v]);
-      std::sort(img.begin(), img.end());
-      auto it = row_of.find(img);
-      ok = it != row_of.end() && it->second == (c + m / 2) % m;
-    }
-    if (!ok) continue;
-    out->block = B;
-    out->sigma_v = sv;
-    out->va.clear();
-    for (int v = 0; v < n; ++v)
-      if ((v % B) < B / 2) out->va.push_back(v);
-    return true;
-  }
-  return false;
+  return true;
 }
 
-bool lane_eligible(const HostGraph& g, bool posterior, std::string* why) {
+bool fixed_point_free(const std::vector<int>& p) {
+  for (size_t i = 0; i < p.size(); ++i)
+    if (p[i] == (int)i) return false;
+  return true;
+}
+
+std::vector<int> compose(const std::vector<int>& a, const std::vector<int>& b) {  // a after b
+  std::vector<int> r(b.size());
+  for (size_t i = 0; i < b.size(); ++i) r[i] = a[b[i]];
+  return r;
+}
+
+}  // namespace
+
+void find_group(const HostGraph& g, int max_lanes, LaneGroup* out) {
+  const int n = g.n, m = g.m;
+  out->lanes = 1;
+  out->v.assign(1, std::vector<int>(n));
+  out->c.assign(1, std::vector<int>(m));
+  std::iota(out->v[0].begin(), out->v[0].end(), 0);
+  std::iota(out->c[0].begin(), out->c[0].end(), 0);
+  out->off = {0};
+  out->block.clear();
+  if (max_lanes < 2 || n % 2 || m % 2) return;
+  std::map<std::vector<int>, int> row_of;
+  for (int c = 0; c < m; ++c) {
+    if (g.rows[c].empty()) return;
+    row_of[g.rows[c]] = c;
+  }
+  if ((int)row_of.size() != m) return;  // repeated rows: a check is not determined by its support
+  // candidate involutions: within blocks of B consecutive columns, shift by B/2
+  std::vector<int> blocks;
+  std::vector<std::vector<int>> inv_v, inv_c;
+  for (int B = n; B >= 2; --B) {
+    if (n % B || B % 2) continue;
+    std::vector<int> sv(n), sc;
+    for (int v = 0; v < n; ++v) sv[v] = (v / B) * B + ((v % B) + B / 2) % B;
+    if (!induced_checks(g, row_of, sv, &sc) || !fixed_point_free(sc)) continue;
+    blocks.push_back(B);
+    inv_v.push_back(sv);
+    inv_c.push_back(sc);
+  }
+  if (blocks.empty()) return;
+  if (max_lanes >= 4) {
+    // two generators whose half-block bits are independent (the smaller block
+    // divides half the larger), so that lane k's columns are lane 0's shifted
+    // by a constant
+    for (size_t i = 0; i < blocks.size(); ++i)
+      for (size_t j = i + 1; j < blocks.size(); ++j) {
+        if ((blocks[i] / 2) % blocks[j]) continue;
+        const auto pv = compose(inv_v[i], inv_v[j]), pc = compose(inv_c[i], inv_c[j]);
+        if (pv != compose(inv_v[j], inv_v[i]) || pc != compose(inv_c[j], inv_c[i])) continue;
+        if (!fixed_point_free(pv) || !fixed_point_free(pc)) continue;
+        out->lanes = 4;
+        out->v = {out->v[0], inv_v[i], inv_v[j], pv};
+        out->c = {out->c[0], inv_c[i], inv_c[j], pc};
+        out->off = {0, blocks[i] / 2, blocks[j] / 2, blocks[i] / 2 + blocks[j] / 2};
+        out->block = {blocks[i], blocks[j]};
+        return;
+      }
+  }
+  out->lanes = 2;
+  out->v = {out->v[0], inv_v[0]};
+  out->c = {out->c[0], inv_c[0]};
+  out->off = {0, blocks[0] / 2};
+  out->block = {blocks[0]};
+}
+
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::string* why) {
   auto fail = [&](const char* msg) {
     if (why) *why = msg;
     return false;
   };
-  if (g.n > 250) return fail("more than 250 columns");
-  if (g.m > 160) return fail("more than 160 checks");
+  if (g.n > 1024) return fail("more than 1024 columns");
+  if (g.m > 1024) return fail("more than 1024 checks");
   if (max_deg(g.rows) > 15) return fail("check degree above 15");
   if (max_deg(g.cols) > 16) return fail("column degree above 16");
   if (max_deg(g.drows) > 32) return fail("degeneracy-matrix row degree above 32");
+  LaneGroup grp;
+  find_group(g, max_lanes, &grp);
+  const int G = grp.lanes;
+  if (g.n / G > 128) return fail("more than 128 columns per lane");
+  if (g.m / G > 80) return fail("more than 80 checks per lane");
   size_t dnnz = 0;
   for (auto& r : g.drows) dnnz += r.size();
-  const size_t lds = (size_t)g.n * 65 * 4 * (posterior ? 2 : 1) + (g.drows.size() + 1) * 4 + dnnz * 2 +
-                     ((g.n + 31) / 32) * 8 + (size_t)g.n * 6;
+  const size_t lstr = 64 / G + 1;
+  const size_t lds = (size_t)g.n * lstr * 4 * (posterior ? 2 : 1) + g.drows.size() * max_deg(g.drows) * 2 +
+                     g.drows.size() + (size_t)G * ((g.n / G + 31) / 32) * 4 + (size_t)g.n * 2 +
+                     (size_t)G * (g.n / G) * 4 + 32 * (size_t)G * ((g.m / G + 31) / 32) * 4;
   if (lds > 64 * 1024) return fail("per-wave LDS above 64 KiB");
   return true;
 }
 
-std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes) {
   const int n = g.n, m = g.m, md = (int)g.drows.size();
-  Pairing pr;
-  const bool paired = find_pairing(g, &pr);
-  // ---- slots (checks held by one lane), rows (columns of one lane) ----
-  const int nslots = paired ? m / 2 : m;
-  const int nrows = paired ? n / 2 : n;
-  std::vector<int> row_col(nrows);  // column handled by lane A (or the single lane) at row i
-  if (paired) row_col = pr.va;
-  else std::iota(row_col.begin(), row_col.end(), 0);
-  // events of row i: (slot, remote, check of lane A's edge)
+  LaneGroup grp;
+  find_group(g, max_lanes, &grp);
+  const int G = grp.lanes;
+  // rows: lane 0's columns (lower half of every generator's block), ascending
+  std::vector<int> row_col;
+  for (int v = 0; v < n; ++v) {
+    bool low = true;
+    for (int B : grp.block) low = low && (v % B) < B / 2;
+    if (low) row_col.push_back(v);
+  }
+  const int nrows = (int)row_col.size();
+  // slots: check orbits, lane 0 holding the smallest check of each
+  std::vector<int> slot_of(m, -1), rel_of(m, 0), slot_base;
+  for (int c = 0; c < m; ++c) {
+    if (slot_of[c] >= 0) continue;
+    const int s = (int)slot_base.size();
+    slot_base.push_back(c);
+    for (int k = 0; k < G; ++k) {
+      slot_of[grp.c[k][c]] = s;
+      rel_of[grp.c[k][c]] = k;
+    }
+  }
+  const int nslots = (int)slot_base.size();
+  // events of row i: lane 0's column's edges in ascending check order
   struct Ev {
-    int slot, remote, chk;
+    int slot, rel, chk;
   };
   std::vector<std::vector<Ev>> ev(nrows);
   std::vector<std::vector<int>> items(nrows);
-  for (int i = 0; i < nrows; ++i) {
-    const int v = row_col[i];
-    for (int c : g.cols[v]) {  // ascending checks
-      const int slot = paired ? (c < m / 2 ? c : c - m / 2) : c;
-      const int remote = paired && c >= m / 2;
-      ev[i].push_back({slot, remote, c});
-      items[i].push_back(slot);
+  for (int i = 0; i < nrows; ++i)
+    for (int c : g.cols[row_col[i]]) {
+      ev[i].push_back({slot_of[c], rel_of[c], c});
+      items[i].push_back(slot_of[c]);
     }
-  }
   std::vector<int> sdeg(nslots, 0);
   for (auto& e : ev)
     for (auto& x : e) ++sdeg[x.slot];
@@ -170,39 +240,51 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
     bit += bits;
   }
   const int nwc = word + 1;
+  const int spw = std::max(1, (nslots + 31) / 32);
   size_t dnnz = 0;
   for (auto& r : g.drows) dnnz += r.size();
-
   bool uniform_drows = !g.drows.empty();
   for (auto& r : g.drows) uniform_drows = uniform_drows && (int)r.size() == max_deg(g.drows);
+
   std::ostringstream o;
-  o << "#define NB_M " << m << "\n#define NB_N " << n << "\n#define NB_MD " << md
-    << "\n#define NB_SW32 " << (m + 31) / 32 << "\n#define NB_SW64 " << (m + 63) / 64
-    << "\n#define NB_NW64 " << (n + 63) / 64 << "\n#define NB_NC32 " << (n + 31) / 32
-    << "\n#define NB_SLOTS " << nslots << "\n#define NB_ROWS " << nrows << "\n#define NB_RC32 "
-    << (nrows + 31) / 32 << "\n#define NB_NWC " << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1)
-    << "\n#define NB_DMAXROW " << std::max(1, max_deg(g.drows)) << "\n#define NB_DUNIFORM " << (uniform_drows ? 1 : 0)
-    << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0)
-    << "\n#define NB_PAIRED " << (paired ? 1 : 0) << "\n#define NB_HALFOFF " << (paired ? pr.block / 2 : 0)
-    << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0)
-    << "\n";
-  // column -> (row, lane B?) map for the cooperative DC / output code, and the
-  // column of lane B at each row
+  o << "#define NB_M " << m << "\n#define NB_N " << n << "\n#define NB_MD " << md << "\n#define NB_SW64 "
+    << (m + 63) / 64 << "\n#define NB_SPW " << spw << "\n#define NB_NW64 " << (n + 63) / 64 << "\n#define NB_SLOTS "
+    << nslots << "\n#define NB_ROWS " << nrows << "\n#define NB_RC32 " << (nrows + 31) / 32 << "\n#define NB_NWC "
+    << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1) << "\n#define NB_DMAXROW "
+    << std::max(1, max_deg(g.drows)) << "\n#define NB_DUNIFORM " << (uniform_drows ? 1 : 0)
+    << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0) << "\n#define NB_G " << G;
+  for (int k = 1; k < 4; ++k) o << "\n#define NB_LOFF" << k << " " << (k < G ? grp.off[k] : 0);
+  o << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0) << "\n";
+  // column -> (row << 2 | lane in group), for the cooperative DC code
   o << "__device__ __constant__ const short nb_col_row[" << n << "] = {";
   {
     std::vector<int> cr(n, -1);
-    for (int i = 0; i < nrows; ++i) {
-      cr[row_col[i]] = i << 1;
-      if (paired) cr[pr.sigma_v[row_col[i]]] = (i << 1) | 1;
-    }
+    for (int k = 0; k < G; ++k)
+      for (int i = 0; i < nrows; ++i) cr[grp.v[k][row_col[i]]] = (i << 2) | k;
     for (int v = 0; v < n; ++v) o << cr[v] << (v + 1 < n ? "," : "");
   }
   o << "};\n";
-  o << "__device__ __constant__ const short nb_row_col[2][" << nrows << "] = {{";
-  for (int i = 0; i < nrows; ++i) o << row_col[i] << (i + 1 < nrows ? "," : "");
-  o << "},{";
-  for (int i = 0; i < nrows; ++i) o << (paired ? pr.sigma_v[row_col[i]] : row_col[i]) << (i + 1 < nrows ? "," : "");
-  o << "}};\n";
+  o << "__device__ __constant__ const short nb_row_col[" << G << "][" << nrows << "] = {";
+  for (int k = 0; k < G; ++k) {
+    o << "{";
+    for (int i = 0; i < nrows; ++i) o << grp.v[k][row_col[i]] << (i + 1 < nrows ? "," : "");
+    o << "}" << (k + 1 < G ? "," : "");
+  }
+  o << "};\n";
+  // Syndrome words of every lane of a group in slot order, from the shot's
+  // packed syndrome s32[] (32-bit words): out[k * NB_SPW + w] bit j = syndrome
+  // bit of the check that lane k holds in slot 32 w + j.
+  o << "#define NB_PREP(s32, out) do { \\\n";
+  for (int k = 0; k < G; ++k)
+    for (int w = 0; w < spw; ++w) {
+      o << "out[" << k * spw + w << "] = 0u";
+      for (int j = 0; j < 32 && 32 * w + j < nslots; ++j) {
+        const int c = grp.c[k][slot_base[32 * w + j]];
+        o << " | (((s32[" << (c >> 5) << "] >> " << (c & 31) << ") & 1u) << " << j << ")";
+      }
+      o << "; \\\n";
+    }
+  o << "} while (0)\n";
 
   o << "#define NB_SWEEP() do { \\\n";
   for (int s = 0; s < nslots; ++s)
@@ -213,33 +295,41 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
     o << "{ float L = NB_LAM(" << i << ", " << row_col[i] << "); \\\n";
     for (int j = 0; j < dv; ++j) {
       const int s = e[j].slot, d = sdeg[s], b = d - 1 - pos[i][j];
-      o << "const float r" << j << " = " << (e[j].remote ? "NB_SWAPF(" : "(") << "NB_DEC(" << s << ", " << cw[s]
-        << ", " << (off[s] + d + b) << ", " << (off[s] + b) << ")); \\\n";
+      o << "const float r" << j << " = NB_XF" << e[j].rel << "(NB_DEC(" << s << ", " << cw[s] << ", "
+        << (off[s] + d + b) << ", " << (off[s] + b) << ")); \\\n";
     }
-    // summation order: lane A in ascending checks (instruction order); lane B
-    // in ascending sigma(checks)
-    std::vector<int> perm(dv);
-    std::iota(perm.begin(), perm.end(), 0);
-    if (paired) {
+    // summation: lane k adds in ascending order of its own checks
+    std::vector<std::vector<int>> perm(G, std::vector<int>(dv));
+    for (int k = 0; k < G; ++k) {
       std::vector<int> img(dv);
-      for (int j = 0; j < dv; ++j) img[j] = (e[j].chk + m / 2) % m;
-      std::sort(perm.begin(), perm.end(), [&](int a, int b) { return img[a] < img[b]; });
+      for (int j = 0; j < dv; ++j) img[j] = grp.c[k][e[j].chk];
+      std::iota(perm[k].begin(), perm[k].end(), 0);
+      std::sort(perm[k].begin(), perm[k].end(), [&](int a, int b) { return img[a] < img[b]; });
     }
     for (int p = 0; p < dv; ++p) {
-      if (perm[p] == p) o << "L = L + r" << p << "; \\\n";
-      else o << "L = L + NB_PICK(r" << p << ", r" << perm[p] << "); \\\n";
+      std::vector<std::pair<int, int>> src;  // (edge, mask of lanes taking it)
+      for (int k = 0; k < G; ++k) {
+        auto it = std::find_if(src.begin(), src.end(),
+                               [&](const std::pair<int, int>& x) { return x.first == perm[k][p]; });
+        if (it == src.end()) src.push_back({perm[k][p], 1 << k});
+        else it->second |= 1 << k;
+      }
+      std::string x = "r" + std::to_string(src.back().first);
+      for (int q = (int)src.size() - 2; q >= 0; --q)
+        x = "(NB_IN(" + std::to_string(src[q].second) + ") ? r" + std::to_string(src[q].first) + " : " + x + ")";
+      o << "L = L + " << x << "; \\\n";
     }
     o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
-    bool any_remote = false;
-    for (int j = 0; j < dv; ++j) any_remote |= e[j].remote != 0;
-    if (any_remote) o << "const u32 evx = NB_SWAPU(ev); \\\n";
+    int kinds = 0;
+    for (int j = 0; j < dv; ++j) kinds |= 1 << e[j].rel;
+    for (int r = 1; r < 4; ++r)
+      if (kinds & (1 << r)) o << "const u32 ev" << r << " = NB_XU" << r << "(ev); \\\n";
     for (int j = 0; j < dv; ++j) {
       const int s = e[j].slot, d = sdeg[s], p = pos[i][j], b = d - 1 - p;
       const char* acc = p == 0 ? "NB_ACC0(" : "NB_ACC(";
-      if (e[j].remote)
-        o << "{ const float q = NB_SWAPF(NB_Q(L, r" << j << ")); " << acc << s << ", q, evx, " << b << "); } \\\n";
-      else
-        o << "{ const float q = NB_Q(L, r" << j << "); " << acc << s << ", q, ev, " << b << "); } \\\n";
+      const std::string evn = e[j].rel ? "ev" + std::to_string(e[j].rel) : "ev";
+      o << "{ const float q = NB_XF" << e[j].rel << "(NB_Q(L, r" << j << ")); " << acc << s << ", q, " << evn << ", "
+        << b << "); } \\\n";
       if (p == d - 1) o << "NB_FIN(" << s << ", " << cw[s] << ", " << off[s] << ", " << d << "); \\\n";
     }
     o << "} \\\n";
@@ -248,12 +338,11 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
     if (!sdeg[s]) o << "U |= __builtin_amdgcn_ubfe(S[" << (s >> 5) << "], " << (s & 31) << ", 1) << 31; \\\n";
   o << "} while (0)\n";
   // Check state after the first iteration of a first pass with equal priors
-  // lambda > 0 (every q = lambda): alpha*min1 = alpha*lambda, alpha*min2 the
-  // same (or alpha*lsat for a check of degree 1), argmin the first edge, and
-  // every r sign equal to the check's syndrome bit.
-  // A check of degree >= 2 gets no argmin bit (its two minima are equal, so
-  // every edge reads alpha*min1 and A2 need not be written); a check of
-  // degree 1 marks its only edge, which reads alpha*lsat.
+  // lambda > 0 (every q = lambda): alpha*min1 = alpha*lambda, the same second
+  // minimum (or alpha*lsat for a check of degree 1), and every r sign equal to
+  // the check's syndrome bit.  A check of degree >= 2 gets no argmin bit (its
+  // two minima are equal, so every edge reads alpha*min1 and A2 need not be
+  // written); a check of degree 1 marks its only edge, which reads alpha*lsat.
   o << "#define NB_INIT1() do { \\\n";
   {
     std::vector<uint32_t> amc(nwc, 0u);
@@ -270,7 +359,11 @@ std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior) {
       << mask << "u; \\\n";
   }
   o << "} while (0)\n";
-  return o.str();
+  LaneSpec out;
+  out.src = o.str();
+  out.lanes = G;
+  out.spw = spw;
+  return out;
 }
 
 }  // namespace bpdc

@@ -14,16 +14,33 @@ struct HostGraph {
   std::vector<std::vector<int>> drows;  // D: columns of each row, ascending
 };
 
-// An involutive automorphism of H used to split a shot over two lanes: columns
-// shifted by half a block of size `block`, checks by m/2.
-struct Pairing {
-  int block = 0;
-  std::vector<int> sigma_v;  // column permutation
-  std::vector<int> va;       // columns of lane A (one per orbit), ascending
+// A group of automorphisms of H acting freely on columns and on checks, of
+// order 1, 2 or 4: the trivial group, one involution, or two commuting
+// involutions.  Each generator shifts the columns by half a block within
+// blocks of `block` consecutive columns (the translations of bivariate
+// bicycle and toric codes are of this kind).  Element k (k = 0 .. lanes-1) is
+// the product of the generators selected by the bits of k, so elements
+// compose by XOR of their indices.  Lane 0 of a shot's group holds the
+// columns that lie in the lower half of their block for every generator;
+// lane k holds their images under element k, which are lane 0's columns
+// shifted by off[k].
+struct LaneGroup {
+  int lanes = 1;
+  std::vector<std::vector<int>> v;  // v[k][column]
+  std::vector<std::vector<int>> c;  // c[k][check]
+  std::vector<int> off;             // off[k]: column offset of lane k
+  std::vector<int> block;           // block size of each generator
 };
 
-bool find_pairing(const HostGraph& g, Pairing* out);
-bool lane_eligible(const HostGraph& g, bool posterior, std::string* why);
-std::string lane_spec(const HostGraph& g, bool posterior, bool uniform_prior);
+// The layout the generator chose, with the kernel source.
+struct LaneSpec {
+  std::string src;
+  int lanes = 1;  // lanes per shot
+  int spw = 1;    // 32-bit syndrome words per lane (slot order)
+};
+
+void find_group(const HostGraph& g, int max_lanes, LaneGroup* out);
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::string* why);
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes);
 
 }  // namespace bpdc

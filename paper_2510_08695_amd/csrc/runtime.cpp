@@ -188,7 +188,10 @@ struct bpdc_code_s {
 struct LaneKernel {
   hipModule_t mod = nullptr;
   hipFunction_t fn = nullptr;
+  hipFunction_t prep = nullptr;  // syndrome preparation kernel of the same module
   int grid = 0;
+  int lanes = 1;                 // lanes per shot
+  int spw = 1;                   // prepared syndrome words per lane
   std::string cache_path;
 };
 
@@ -220,7 +223,7 @@ namespace {
 
 // Mirrors LaneArgs in lane_kernel.hip.
 struct LaneArgsHost {
-  const unsigned long long* syn;
+  const unsigned* synp;
   long long B;
   long long shot_offset;
   unsigned long long* corr;
@@ -246,6 +249,13 @@ struct LaneArgsHost {
   int skip0;
 };
 
+// Largest lane group the lane kernel may use for one shot (1, 2 or 4).
+int lane_max_lanes() {
+  const char* e = getenv("BPDC_LANE_MAX_LANES");
+  const int v = e ? atoi(e) : 4;
+  return v >= 4 ? 4 : (v >= 2 ? 2 : 1);
+}
+
 bool uniform_prior(const bpdc_code_s* c) {
   for (float x : c->lam)
     if (x != c->lam[0]) return false;
@@ -254,13 +264,17 @@ bool uniform_prior(const bpdc_code_s* c) {
 
 bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) {
   std::string why;
-  if (!bpdc::lane_eligible(c->g, posterior, &why))
+  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  bpdc_status st = lane_code_object(bpdc::lane_spec(c->g, posterior, uniform_prior(c)), &image, &lk->cache_path);
+  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes());
+  bpdc_status st = lane_code_object(spec.src, &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
+  lk->lanes = spec.lanes;
+  lk->spw = spec.spw;
   HIP_TRY(hipModuleLoadData(&lk->mod, image.data()));
   HIP_TRY(hipModuleGetFunction(&lk->fn, lk->mod, "bpdc_lane_kernel"));
+  HIP_TRY(hipModuleGetFunction(&lk->prep, lk->mod, "bpdc_lane_prepare"));
   int nb = 0;
   HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lk->fn, 64, 0));
   if (nb < 1) return fail(BPDC_ERR_UNSUPPORTED, "lane kernel does not fit on a compute unit");
@@ -270,13 +284,26 @@ bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) 
 
 const size_t kLaneWs = 256;
 
+// queue counter, then the prepared syndrome words [B][lanes][spw]
+size_t lane_ws_bytes(const LaneKernel& lk, int64_t B) {
+  return kLaneWs + (((size_t)B * lk.lanes * lk.spw * 4 + 255) & ~(size_t)255);
+}
+
 bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, const bpdc::DecodeIO& io,
                         void* ws, hipStream_t stream) {
   unsigned long long* queue = (unsigned long long*)ws;
   (void)hipGetLastError();
   HIP_TRY(bpdc::fill_u64((uint64_t*)queue, 0, 1, stream));
+  unsigned* synp = (unsigned*)((char*)ws + kLaneWs);
+  {
+    const long long B = io.B;
+    const unsigned long long* syn = (const unsigned long long*)io.syn;
+    void* pargs[] = {&syn, (void*)&B, &synp};
+    HIP_TRY(hipModuleLaunchKernel(cp.lane.prep, (unsigned)((io.B + 255) / 256), 1, 1, 256, 1, 1, 0, stream, pargs,
+                                  nullptr));
+  }
   LaneArgsHost a;
-  a.syn = (const unsigned long long*)io.syn;
+  a.synp = synp;
   a.B = io.B;
   a.shot_offset = io.shot_offset;
   a.corr = (unsigned long long*)io.corr;
@@ -304,7 +331,7 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   a.a1_init = p->kp.alpha * lam0;
   a.a2_init1 = p->kp.alpha * p->kp.lsat;
   void* args[] = {&a};
-  const int64_t want = (io.B + 63) / 64;
+  const int64_t want = (io.B * cp.lane.lanes + 63) / 64;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cp.lane.grid, want));
   HIP_TRY(hipModuleLaunchKernel(cp.lane.fn, grid, 1, 1, 64, 1, 1, 0, stream, args, nullptr));
   return BPDC_OK;
@@ -616,10 +643,11 @@ bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t p
   g.drows.resize(D->rows);
   for (int r = 0; r < D->rows; ++r)
     for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
-  if (!bpdc::lane_eligible(g, posterior != 0, &why))
+  if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0), &image, nullptr);
+  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes()).src, &image,
+                          nullptr);
 }
 
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
@@ -674,7 +702,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
       continue;
     }
     std::string why_lane, why_group;
-    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, &why_lane);
+    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), &why_lane);
     const bool group_ok = group_fits(p.get(), c->dev, &why_group);
     if (kernel == BPDC_KERNEL_LANE) {
       if ((st = build_lane(c, posterior, p->num_cu, &cp.lane)) != BPDC_OK) return st;
@@ -774,6 +802,7 @@ bpdc_status bpdc_workspace_size(bpdc_plan p, int32_t code, int64_t B, size_t* by
   const CodePlan& cp = p->per_code[code];
   switch (cp.kernel) {
     case BPDC_KERNEL_PLAIN: *bytes = bpdc::plain_workspace_bytes(p->codes[code]->dev, B); break;
+    case BPDC_KERNEL_LANE: *bytes = lane_ws_bytes(cp.lane, B); break;
     default: *bytes = kLaneWs; break;
   }
   return BPDC_OK;

@@ -135,13 +135,7 @@ def test_parameter_variants_bit_exact(P, variant):
     if variant == "posterior_bb":
         prm.second_pass_prior = P.PRIOR_POSTERIOR
         sp_name = "posterior"
-    kernels = (P.KERNEL_LANE, P.KERNEL_PLAIN)
-    if variant == "posterior_bb":
-        # a per-lane second-pass prior does not fit the lane kernel's LDS for n = 144
-        with pytest.raises(P.BpdcError, match="unsupported"):
-            P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
-        kernels = (P.KERNEL_PLAIN,)
-    for kid in kernels:
+    for kid in (P.KERNEL_LANE, P.KERNEL_PLAIN):
         plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
         g = gpu_decode(plan, code, sh.syndromes, shot_offset=3)
         ref = oracle.decode(code, sh.syndromes, oracle_params(prm, sp_name), precision="f32", shot_offset=3)
