@@ -68,7 +68,9 @@ struct LaneArgs {
 // group store with the same offsets).  The odd strides keep column-wise reads
 // free of bank conflicts.
 #define NB_LSTR (64 / NB_G + 1)
+#ifndef NB_CHUNK
 #define NB_CHUNK 32   // largest number of shots a wave claims at once
+#endif
 
 namespace bpdc_lane {
 using bpdc_dev::u32;
@@ -187,7 +189,12 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 #define NB_LAM(i, v) NB_LAM1(i)
 #endif
 
-extern "C" __global__ void __launch_bounds__(64, 1) bpdc_lane_kernel(LaneArgs a) {
+#ifdef NB_WAVES_PER_EU
+#define NB_KATTR __attribute__((amdgpu_flat_work_group_size(64, 64), amdgpu_waves_per_eu(NB_WAVES_PER_EU, NB_WAVES_PER_EU)))
+#else
+#define NB_KATTR __launch_bounds__(64, 1)
+#endif
+extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
   using namespace bpdc_lane;
   __shared__ float sL[NB_N * NB_LSTR];
 #if NB_POSTERIOR

@@ -126,11 +126,60 @@ const char* kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-co
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
 const int kNumRtcOpts = sizeof(kRtcOpts) / sizeof(kRtcOpts[0]);
 
+// hipRTC loaded from the ROCm installation by full path instead of linked:
+// a process that loaded another copy of hipRTC / comgr first (frameworks ship
+// their own) would otherwise compile the lane kernel with that compiler, and
+// its code for gfx950 is not the same.
+struct Rtc {
+  bool ok = false;
+  std::string why;
+  hiprtcResult (*create)(hiprtcProgram*, const char*, const char*, int, const char**, const char**) = nullptr;
+  hiprtcResult (*compile)(hiprtcProgram, int, const char**) = nullptr;
+  hiprtcResult (*log_size)(hiprtcProgram, size_t*) = nullptr;
+  hiprtcResult (*log)(hiprtcProgram, char*) = nullptr;
+  hiprtcResult (*code_size)(hiprtcProgram, size_t*) = nullptr;
+  hiprtcResult (*code)(hiprtcProgram, char*) = nullptr;
+  hiprtcResult (*destroy)(hiprtcProgram*) = nullptr;
+};
+
+const Rtc& rtc() {
+  static const Rtc r = [] {
+    Rtc x;
+    std::vector<std::string> cand;
+    if (const char* e = getenv("ROCM_PATH"))
+      if (*e) cand.push_back(std::string(e) + "/lib/libhiprtc.so");
+    cand.push_back("/opt/rocm/lib/libhiprtc.so");
+    // a namespace of its own, so that hipRTC resolves comgr (and everything
+    // else) from the installation and not from libraries already loaded
+    void* h = nullptr;
+    for (auto& c : cand)
+      if ((h = dlmopen(LM_ID_NEWLM, c.c_str(), RTLD_NOW | RTLD_LOCAL)) != nullptr) break;
+    if (!h) {
+      x.why = "libhiprtc.so not found under $ROCM_PATH/lib or /opt/rocm/lib";
+      return x;
+    }
+    x.create = (decltype(x.create))dlsym(h, "hiprtcCreateProgram");
+    x.compile = (decltype(x.compile))dlsym(h, "hiprtcCompileProgram");
+    x.log_size = (decltype(x.log_size))dlsym(h, "hiprtcGetProgramLogSize");
+    x.log = (decltype(x.log))dlsym(h, "hiprtcGetProgramLog");
+    x.code_size = (decltype(x.code_size))dlsym(h, "hiprtcGetCodeSize");
+    x.code = (decltype(x.code))dlsym(h, "hiprtcGetCode");
+    x.destroy = (decltype(x.destroy))dlsym(h, "hiprtcDestroyProgram");
+    x.ok = x.create && x.compile && x.log_size && x.log && x.code_size && x.code && x.destroy;
+    if (!x.ok) x.why = "libhiprtc.so lacks an expected entry point";
+    return x;
+  }();
+  return r;
+}
+
 // Compile (or load from the disk cache) the lane kernel for one code.
 bpdc_status lane_code_object(const std::string& spec, std::vector<char>* image, std::string* path_out) {
   std::string opts;
   for (int i = 0; i < kNumRtcOpts; ++i) opts += std::string(kRtcOpts[i]) + " ";
-  const std::string full = "using u32 = unsigned int;\n" + std::string(kLaneDeviceSrc) + "\n" + spec + "\n" +
+  std::string tune;
+  if (const char* w = getenv("BPDC_LANE_WPE")) tune += "#define NB_WAVES_PER_EU " + std::string(w) + "\n";
+  if (const char* w = getenv("BPDC_LANE_CHUNK")) tune += "#define NB_CHUNK " + std::string(w) + "\n";
+  const std::string full = "using u32 = unsigned int;\n" + std::string(kLaneDeviceSrc) + "\n" + tune + spec + "\n" +
                            std::string(kLaneKernelSrc);
   char key[32];
   snprintf(key, sizeof(key), "%016llx", (unsigned long long)fnv1a(opts + full));
@@ -147,23 +196,25 @@ bpdc_status lane_code_object(const std::string& spec, std::vector<char>* image, 
       if (!image->empty()) return BPDC_OK;
     }
   }
+  const Rtc& R = rtc();
+  if (!R.ok) return fail(BPDC_ERR_UNSUPPORTED, "cannot compile the lane kernel: %s", R.why.c_str());
   hiprtcProgram prog;
-  if (hiprtcCreateProgram(&prog, full.c_str(), "bpdc_lane.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+  if (R.create(&prog, full.c_str(), "bpdc_lane.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
     return fail(BPDC_ERR_HIP, "hiprtcCreateProgram failed");
-  const hiprtcResult rc = hiprtcCompileProgram(prog, kNumRtcOpts, kRtcOpts);
+  const hiprtcResult rc = R.compile(prog, kNumRtcOpts, kRtcOpts);
   if (rc != HIPRTC_SUCCESS) {
     size_t ls = 0;
-    hiprtcGetProgramLogSize(prog, &ls);
+    R.log_size(prog, &ls);
     std::string log(ls, '\0');
-    if (ls) hiprtcGetProgramLog(prog, &log[0]);
-    hiprtcDestroyProgram(&prog);
+    if (ls) R.log(prog, &log[0]);
+    R.destroy(&prog);
     return fail(BPDC_ERR_HIP, "hipRTC compile of the lane kernel failed: %s", log.substr(0, 800).c_str());
   }
   size_t cs = 0;
-  hiprtcGetCodeSize(prog, &cs);
+  R.code_size(prog, &cs);
   image->resize(cs);
-  hiprtcGetCode(prog, image->data());
-  hiprtcDestroyProgram(&prog);
+  R.code(prog, image->data());
+  R.destroy(&prog);
   const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
   {
     std::ofstream f(tmp, std::ios::binary);
@@ -268,7 +319,8 @@ bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) 
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
   const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes());
-  bpdc_status st = lane_code_object(spec.src, &image, &lk->cache_path);
+  std::string src = spec.src;
+  bpdc_status st = lane_code_object(src, &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
   lk->lanes = spec.lanes;
   lk->spw = spec.spw;
