@@ -30,27 +30,39 @@ OPS_PER_DC_ENTRY = 2                # per nonzero of D on shots that run DC
 
 LANE_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/lane_kernel.hip",
                 "paper_2510_08695_amd/csrc/lane_spec.cpp")
-LANE_COUNTERS = "profiles/bpdc_lane_kernel_bb144_p005_1e6_counters.md"
+GROUP_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/group.hip")
+# committed rocprofv3 counter summaries of the dominant kernel of each workload at its default size
+COUNTERS = {
+    "bb144": (LANE_SOURCES, "profiles/bpdc_lane_kernel_bb144_p005_1e6_counters.md"),
+    "phen": (GROUP_SOURCES, "profiles/k_group_phen_bb288_T18_p0003_1e5_counters.md"),
+    "hgp64": (GROUP_SOURCES, "profiles/k_group_hgp64_counters.md"),
+}
 
 
-def lane_traffic():
-    """HBM bytes per lane-kernel launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a copy of known
-    size), or None once the kernel source differs from the one profiled."""
+def source_sha256(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in LANE_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(workload):
+    """HBM bytes per launch of the workload's dominant kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated
+    against a copy of known size), or None once the kernel source differs from
+    the one profiled."""
+    sources, path = COUNTERS[workload]
     vals = {}
     try:
-        with open(os.path.join(ROOT, LANE_COUNTERS)) as fh:
+        with open(os.path.join(ROOT, path)) as fh:
             for line in fh:
                 k, _, v = line.strip().partition(": ")
                 vals[k] = v
     except OSError:
         return None
-    if vals.get("kernel_source_sha256") != h.hexdigest():
+    if vals.get("kernel_source_sha256") != source_sha256(sources):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -156,7 +168,7 @@ def main():
         "mean_iters": float(iters.sum()) / B,
     }
     achieved = ops_per_step / (launch_ms / 1e3)
-    traffic = lane_traffic() if B == 1_000_000 and p == 0.05 else None
+    traffic = committed_traffic("bb144") if B == 1_000_000 and p == 0.05 else None
     result["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                           "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                           "traffic_unit": "bytes per launch", "algorithmic_bytes": B * (8 * ((code.H.rows + 63) // 64) +
@@ -265,7 +277,7 @@ def _ler(code, errors, corr_words, flags):
     return k / len(flags), [lo, hi]
 
 
-def _single(args, code, B, seed, prm, workload, metric, kernel):
+def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None):
     import torch
     import paper_2510_08695_amd as P
     import synth
@@ -289,7 +301,9 @@ def _single(args, code, B, seed, prm, workload, metric, kernel):
            "shots_per_step": B, "plan": plan.info(0)},
            "ler": ler, "ler_ci95": ci, "dc_rate": n_dc / B, "mean_iters": float(iters.sum()) / B,
            "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS}}
+                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
+                        "traffic": committed_traffic(traffic_key) if traffic_key else None,
+                        "traffic_unit": "bytes per launch", "launch_ms": ms, "ops_per_launch": ops}}
     if not args.no_plain:
         pplan = P.Plan([c], prm, kernel=P.KERNEL_PLAIN)
         pout = pplan.decode(syn)
@@ -326,7 +340,8 @@ def run_phen(args):
     B = min(args.shots, 100_000)
     res = _single(args, code, B, 3, prm, f"BB[[288,12,18]] phenomenological T=18 p=0.003 ({args.dem_form} "
                   f"time boundary, {code.H.rows}x{code.n}), {B} shots, alpha=0.625, T=1000+1000",
-                  "shots/s BP+DC phenomenological BB288 T=18", P.KERNEL_GROUP)
+                  "shots/s BP+DC phenomenological BB288 T=18", P.KERNEL_GROUP,
+                  traffic_key="phen" if (B == 100_000 and not final) else None)
     print(json.dumps(res), flush=True)
 
 
@@ -376,7 +391,9 @@ def run_hgp64(args):
                       "plan_seconds": plan_s, "tile": {"threads": plan.info(int(np.argmax([c.n for c in codes])))["threads"]}},
            "dc_rate": float(((fl & 2) != 0).mean()), "mean_iters": float(it.sum()) / B,
            "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS}}
+                        "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
+                        "traffic": committed_traffic("hgp64"), "traffic_unit": "bytes per launch",
+                        "launch_ms": ms, "ops_per_launch": ops}}
     if not args.no_plain:
         # plain per-code launches over the same shots
         pplan = P.Plan(handles, prm, kernel=P.KERNEL_PLAIN)

@@ -69,7 +69,7 @@ struct LaneArgs {
 // free of bank conflicts.
 #define NB_LSTR (64 / NB_G + 1)
 #ifndef NB_CHUNK
-#define NB_CHUNK 32   // largest number of shots a wave claims at once
+#define NB_CHUNK 16   // largest number of shots a wave claims at once
 #endif
 
 namespace bpdc_lane {

@@ -169,8 +169,6 @@ bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::strin
   const int G = grp.lanes;
   if (g.n / G > 128) return fail("more than 128 columns per lane");
   if (g.m / G > 80) return fail("more than 80 checks per lane");
-  size_t dnnz = 0;
-  for (auto& r : g.drows) dnnz += r.size();
   const size_t lstr = 64 / G + 1;
   const size_t lds = (size_t)g.n * lstr * 4 * (posterior ? 2 : 1) + g.drows.size() * max_deg(g.drows) * 2 +
                      g.drows.size() + (size_t)G * ((g.n / G + 31) / 32) * 4 + (size_t)g.n * 2 +
