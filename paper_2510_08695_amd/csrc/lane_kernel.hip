@@ -108,11 +108,15 @@ __device__ __forceinline__ float cutsel(float L, u32 cw, const int b, u32 infbit
 }
 
 // Exchange with lane (lane xor J) of the same group of four: one DPP quad
-// permutation (quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]).
+// permutation (quad_perm [1,0,3,2], [2,3,0,1], [3,2,1,0]).  Every source
+// lane of a quad permutation is valid and the sweep runs with all lanes
+// enabled, so bound_ctrl (zero for invalid sources) never applies; it lets
+// the compiler fold the permutation into the consuming VOP2 instruction
+// (v_add_f32_dpp, v_sub_f32_dpp, v_xor_b32_dpp) instead of a separate move.
 template <int J>
 __device__ __forceinline__ u32 xchgu(u32 x) {
   constexpr int ctrl = J == 1 ? 0xB1 : (J == 2 ? 0x4E : 0x1B);
-  return (u32)__builtin_amdgcn_mov_dpp((int)x, ctrl, 0xF, 0xF, false);
+  return (u32)__builtin_amdgcn_mov_dpp((int)x, ctrl, 0xF, 0xF, true);
 }
 template <int J>
 __device__ __forceinline__ float xchgf(float x) {
@@ -128,37 +132,41 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 }  // namespace bpdc_lane
 
 // Accumulate q into the next state of slot s (bit b): first event / later events.
-#define NB_ACC0(s, q, ev, b)                                   \
+#define NB_ACC0(s, q, b)                                       \
   {                                                            \
     const float a_ = fabsf(q);                                 \
     m1_##s = bpdc_lane::absmin(q, LS);                         \
     m2_##s = LS;                                               \
     am_##s = (a_ < LS) ? (1u << (b)) : 0u;                     \
     sb_##s = __float_as_uint(q) >> 31;                         \
-    ep_##s = (ev);                                             \
   }
-#define NB_ACC(s, q, ev, b)                                    \
+#define NB_ACC(s, q, b)                                        \
   {                                                            \
     const float a_ = fabsf(q);                                 \
     am_##s = (a_ < m1_##s) ? (1u << (b)) : am_##s;             \
     m2_##s = __builtin_amdgcn_fmed3f(a_, m1_##s, m2_##s);      \
     m1_##s = bpdc_lane::absmin(q, m1_##s);                     \
     sb_##s = __builtin_amdgcn_alignbit(sb_##s, __float_as_uint(q), 31); \
-    ep_##s ^= (ev);                                            \
   }
+// Stop-test parity of slot s: xor of its columns' hard decisions (bit 31 of
+// ev), starting from the check's syndrome bit.
+#define NB_EP0(s, ev) ep_##s = (ev) ^ (S[(s) >> 5] << (31 - ((s) & 31)))
+#define NB_EP(s, ev) ep_##s ^= (ev)
 // Complete slot s (degree d, field at bit `off` of W[cw]): r signs =
-// s_c xor parity of all q signs xor own sign; stop-test parity into U.
+// s_c xor parity of all q signs xor own sign; stop-test parity into U.  Only
+// bit 31 of ev, ep and U is meaningful: ep starts as the check's syndrome bit
+// (placed at bit 31) xor its first column's hard decision.
 #define NB_FIN(s, cw, off, d)                                               \
   {                                                                         \
-    const u32 sc_ = __builtin_amdgcn_ubfe(S[(s) >> 5], (s) & 31, 1);        \
-    const u32 rs_ = ((u32)__builtin_popcount(sb_##s) ^ sc_) & 1u;          \
-    const u32 rm_ = (0u - rs_) & ((1u << (d)) - 1u);                        \
+    /* bit 0 of popcount + (S >> s) = parity of the q signs xor s_c */      \
+    const u32 rs_ = (u32)__builtin_popcount(sb_##s) + (S[(s) >> 5] >> ((s) & 31)); \
+    const u32 rm_ = (0u - (rs_ & 1u)) & ((1u << (d)) - 1u);                 \
     const u32 f_ = (am_##s << (d)) | (sb_##s ^ rm_);                        \
     const u32 fm_ = ((1u << (2 * (d))) - 1u) << (off);                      \
     W[cw] = (W[cw] & ~fm_) | (f_ << (off));                                 \
     A1[s] = alpha * m1_##s;                                                 \
     A2[s] = alpha * m2_##s;                                                 \
-    U |= ep_##s ^ (sc_ << 31);                                              \
+    U |= ep_##s;                                                            \
   }
 #define NB_DEC(s, cw, op, sp) bpdc_lane::dec(A1[s], A2[s], W[cw], op, sp, SIGNMASK)
 #define NB_CUT(L, i) L = bpdc_lane::cutsel(L, C[(i) >> 5], (i) & 31, INFBITS)
@@ -175,8 +183,10 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 #define NB_XU1(x) bpdc_lane::xchgu<1>(x)
 #define NB_XU2(x) bpdc_lane::xchgu<2>(x)
 #define NB_XU3(x) bpdc_lane::xchgu<3>(x)
-// true on the lanes of a group whose index is in the bit mask
-#define NB_IN(mask) ((((mask) >> role) & 1) != 0)
+// a on the lanes of a group whose index is in the bit mask, else b: one
+// v_bfi_b32 with a per-lane mask register (kept in a vector register so that
+// the conditions do not occupy scalar register pairs)
+#define NB_SEL(mask, a, b) __uint_as_float(bpdc_lane::bfi(rolemask[mask], __float_as_uint(a), __float_as_uint(b)))
 
 #if NB_UNIFORM_PRIOR
 #define NB_LAM1(i) LAMU
@@ -230,13 +240,22 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
 
   const int sid = lane / NB_G;  // this lane's shot slot in sL
   const int loff = role == 1 ? NB_LOFF1 : (role == 2 ? NB_LOFF2 : (role == 3 ? NB_LOFF3 : 0));
+  // rolemask[m]: all ones on the lanes whose role is in the bit set m
+  u32 rolemask[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) asm("v_mov_b32 %0, %1" : "=v"(rolemask[m]) : "v"(0u - ((m >> role) & 1u)));
   float* myL = sL + sid + loff * NB_LSTR;
 #if NB_POSTERIOR
   float* myLam2 = sLam2 + sid + loff * NB_LSTR;
 #endif
   const float LS = a.lsat;
   const float alpha = a.alpha;
-  const float LAMU = a.lam_uniform;
+  // the uniform prior in a vector register (an asm copy the compiler cannot
+  // fold back into a scalar operand): the first addition of a column then
+  // takes an exchanged message as a DPP operand, which needs both sources in
+  // vector registers
+  float LAMU;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(LAMU) : "s"(a.lam_uniform));
   const float A1I = a.a1_init, A2I1 = a.a2_init1;
   const u32 SIGNMASK = 0x80000000u, INFBITS = 0x7F800000u;
   // lanes below the first lane of this lane's pair (for numbering new shots)
@@ -260,6 +279,10 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
     // HBM.  The chunk shrinks as the batch runs out (a fraction of what was
     // left at the wave's last claim), so that few claimed shots are still
     // waiting when other waves already idle.
+    long long nshot = -1;  // shot taken by this lane's group in this refill
+    u32 nS[NB_SPW];
+#pragma unroll
+    for (int w = 0; w < NB_SPW; ++w) nS[w] = 0u;
     u64 need = __ballot(want && !dead) & leaders;
     while (need) {
       if (rlo == rhi) {
@@ -295,34 +318,54 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       if ((need >> first) & 1ull) {
         const long long rank = __popcll(need & below);
         if (rank < avail) {
-          const long long my = rlo + rank;
-          shot = my;
+          nshot = rlo + rank;
 #pragma unroll
-          for (int w = 0; w < NB_SPW; ++w) S[w] = sSyn[my - sbase][role * NB_SPW + w];
-#pragma unroll
-          for (int w = 0; w < NB_RC32; ++w) C[w] = 0u;
-#if NB_UNIFORM_PRIOR
-          if (a.skip0) {
-            // the first iteration's check half, written directly
-            NB_INIT1();
-            t = 1;
-          } else
-#endif
-          {
-#pragma unroll
-            for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
-#pragma unroll
-            for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
-            t = 0;
-          }
-          pass = 0;
-          it1 = 0;
+          for (int w = 0; w < NB_SPW; ++w) nS[w] = sSyn[nshot - sbase][role * NB_SPW + w];
           want = false;
         }
       }
       const long long cnt = __popcll(need);
       rlo += cnt < avail ? cnt : avail;
       need = __ballot(want && !dead) & leaders;
+    }
+    // the new shots' initial state, merged with selects rather than under a
+    // branch, so that the state keeps its registers
+    const bool fresh = nshot >= 0;
+    if (__ballot(fresh)) {
+      float A1n[NB_SLOTS], A2n[NB_SLOTS];
+      u32 Wn[NB_NWC];
+      int tn;
+#if NB_UNIFORM_PRIOR
+      if (a.skip0) {
+        // the first iteration's check half, written directly
+#pragma unroll
+        for (int s = 0; s < NB_SLOTS; ++s) { A1n[s] = A1[s]; A2n[s] = A2[s]; }
+        NB_INIT1(Wn, A1n, A2n, nS);
+        tn = 1;
+      } else
+#endif
+      {
+#pragma unroll
+        for (int s = 0; s < NB_SLOTS; ++s) { A1n[s] = 0.0f; A2n[s] = 0.0f; }
+#pragma unroll
+        for (int w = 0; w < NB_NWC; ++w) Wn[w] = 0u;
+        tn = 0;
+      }
+#pragma unroll
+      for (int s = 0; s < NB_SLOTS; ++s) {
+        A1[s] = fresh ? A1n[s] : A1[s];
+        A2[s] = fresh ? A2n[s] : A2[s];
+      }
+#pragma unroll
+      for (int w = 0; w < NB_NWC; ++w) W[w] = fresh ? Wn[w] : W[w];
+#pragma unroll
+      for (int w = 0; w < NB_SPW; ++w) S[w] = fresh ? nS[w] : S[w];
+#pragma unroll
+      for (int w = 0; w < NB_RC32; ++w) C[w] = fresh ? 0u : C[w];
+      shot = fresh ? nshot : shot;
+      t = fresh ? tn : t;
+      pass = fresh ? 0 : pass;
+      it1 = fresh ? 0 : it1;
     }
     if (__ballot(shot >= 0) == 0) break;
 
@@ -448,19 +491,19 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
           }
         }
       }
-      if (to_dc) {
+      // second pass from a zero check state (selects, as for new shots)
 #pragma unroll
-        for (int s = 0; s < NB_SLOTS; ++s) { A1[s] = 0.0f; A2[s] = 0.0f; }
+      for (int s = 0; s < NB_SLOTS; ++s) {
+        A1[s] = to_dc ? 0.0f : A1[s];
+        A2[s] = to_dc ? 0.0f : A2[s];
+      }
 #pragma unroll
-        for (int w = 0; w < NB_NWC; ++w) W[w] = 0u;
-        it1 = t;
-        pass = 1;
-        t = -1;
-      }
-      if (finish) {
-        shot = -1;
-        want = true;
-      }
+      for (int w = 0; w < NB_NWC; ++w) W[w] = to_dc ? 0u : W[w];
+      it1 = to_dc ? t : it1;
+      pass = to_dc ? 1 : pass;
+      t = to_dc ? -1 : t;
+      shot = finish ? -1 : shot;
+      want = want || finish;
     }
     t += 1;
   }

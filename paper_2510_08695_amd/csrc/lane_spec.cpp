@@ -190,10 +190,21 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     if (low) row_col.push_back(v);
   }
   const int nrows = (int)row_col.size();
-  // slots: check orbits, lane 0 holding the smallest check of each
+  // slots: check orbits.  Lane 0 holds the check of each orbit with the most
+  // edges to lane 0's own columns, so that as many edges as possible stay
+  // within a lane (no exchange).
+  std::vector<char> is_row(n, 0);
+  for (int v : row_col) is_row[v] = 1;
   std::vector<int> slot_of(m, -1), rel_of(m, 0), slot_base;
-  for (int c = 0; c < m; ++c) {
-    if (slot_of[c] >= 0) continue;
+  for (int c0 = 0; c0 < m; ++c0) {
+    if (slot_of[c0] >= 0) continue;
+    int c = c0, best = -1;
+    for (int k = 0; k < G; ++k) {
+      const int ck = grp.c[k][c0];
+      int own = 0;
+      for (int v : g.rows[ck]) own += is_row[v];
+      if (own > best) best = own, c = ck;
+    }
     const int s = (int)slot_base.size();
     slot_base.push_back(c);
     for (int k = 0; k < G; ++k) {
@@ -291,11 +302,19 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     const auto& e = ev[i];
     const int dv = (int)e.size();
     o << "{ float L = NB_LAM(" << i << ", " << row_col[i] << "); \\\n";
+    // rr: r of the edge at the lane holding its check.  A value of another
+    // lane of the group is fetched (one DPP permutation) right where it is
+    // consumed, so that the permutation can be folded into the consuming
+    // instruction.
     for (int j = 0; j < dv; ++j) {
       const int s = e[j].slot, d = sdeg[s], b = d - 1 - pos[i][j];
-      o << "const float r" << j << " = NB_XF" << e[j].rel << "(NB_DEC(" << s << ", " << cw[s] << ", "
-        << (off[s] + d + b) << ", " << (off[s] + b) << ")); \\\n";
+      o << "const float rr" << j << " = NB_DEC(" << s << ", " << cw[s] << ", " << (off[s] + d + b) << ", "
+        << (off[s] + b) << "); const float r" << j << " = NB_XF" << e[j].rel << "(rr" << j << "); \\\n";
     }
+    auto xk = [&](int rel, const std::string& v, const char* kind) {
+      if (!rel) return v;
+      return std::string("NB_X") + kind + std::to_string(rel) + "(" + v + ")";
+    };
     // summation: lane k adds in ascending order of its own checks
     std::vector<std::vector<int>> perm(G, std::vector<int>(dv));
     for (int k = 0; k < G; ++k) {
@@ -312,22 +331,25 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
         if (it == src.end()) src.push_back({perm[k][p], 1 << k});
         else it->second |= 1 << k;
       }
-      std::string x = "r" + std::to_string(src.back().first);
+      auto rj = [&](int j) { return "r" + std::to_string(j); };
+      std::string x = rj(src.back().first);
       for (int q = (int)src.size() - 2; q >= 0; --q)
-        x = "(NB_IN(" + std::to_string(src[q].second) + ") ? r" + std::to_string(src[q].first) + " : " + x + ")";
+        x = "NB_SEL(" + std::to_string(src[q].second) + ", " + rj(src[q].first) + ", " + x + ")";
       o << "L = L + " << x << "; \\\n";
     }
     o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
     int kinds = 0;
     for (int j = 0; j < dv; ++j) kinds |= 1 << e[j].rel;
-    for (int r = 1; r < 4; ++r)
-      if (kinds & (1 << r)) o << "const u32 ev" << r << " = NB_XU" << r << "(ev); \\\n";
+    // q = L - r at the lane holding the check, with L of the column's lane;
+    // then the stop-test parities, then the check states
+    (void)kinds;
+    for (int j = 0; j < dv; ++j)
+      o << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << e[j].slot << ", " << xk(e[j].rel, "ev", "U") << "); \\\n";
     for (int j = 0; j < dv; ++j) {
       const int s = e[j].slot, d = sdeg[s], p = pos[i][j], b = d - 1 - p;
       const char* acc = p == 0 ? "NB_ACC0(" : "NB_ACC(";
-      const std::string evn = e[j].rel ? "ev" + std::to_string(e[j].rel) : "ev";
-      o << "{ const float q = NB_XF" << e[j].rel << "(NB_Q(L, r" << j << ")); " << acc << s << ", q, " << evn << ", "
-        << b << "); } \\\n";
+      o << "{ const float q = NB_Q(" << xk(e[j].rel, "L", "F") << ", rr" << j << "); " << acc << s << ", q, " << b
+        << "); } \\\n";
       if (p == d - 1) o << "NB_FIN(" << s << ", " << cw[s] << ", " << off[s] << ", " << d << "); \\\n";
     }
     o << "} \\\n";
@@ -341,19 +363,19 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
   // the check's syndrome bit.  A check of degree >= 2 gets no argmin bit (its
   // two minima are equal, so every edge reads alpha*min1 and A2 need not be
   // written); a check of degree 1 marks its only edge, which reads alpha*lsat.
-  o << "#define NB_INIT1() do { \\\n";
+  o << "#define NB_INIT1(W_, A1_, A2_, S_) do { \\\n";
   {
     std::vector<uint32_t> amc(nwc, 0u);
     for (int s = 0; s < nslots; ++s)
       if (sdeg[s] == 1) amc[cw[s]] |= 1u << (off[s] + 1);
-    for (int w = 0; w < nwc; ++w) o << "W[" << w << "] = " << amc[w] << "u; \\\n";
+    for (int w = 0; w < nwc; ++w) o << "W_[" << w << "] = " << amc[w] << "u; \\\n";
   }
   for (int s = 0; s < nslots; ++s) {
     if (!sdeg[s]) continue;
     const uint32_t mask = ((1u << sdeg[s]) - 1u) << off[s];
-    o << "A1[" << s << "] = A1I; ";
-    if (sdeg[s] == 1) o << "A2[" << s << "] = A2I1; ";
-    o << "W[" << cw[s] << "] |= (u32)__builtin_amdgcn_sbfe((int)S[" << (s >> 5) << "], " << (s & 31) << ", 1) & "
+    o << "A1_[" << s << "] = A1I; ";
+    if (sdeg[s] == 1) o << "A2_[" << s << "] = A2I1; ";
+    o << "W_[" << cw[s] << "] |= (u32)__builtin_amdgcn_sbfe((int)S_[" << (s >> 5) << "], " << (s & 31) << ", 1) & "
       << mask << "u; \\\n";
   }
   o << "} while (0)\n";
