@@ -57,6 +57,13 @@ enum { BPDC_PRIOR_CHANNEL = 0, BPDC_PRIOR_POSTERIOR = 1 };
  * lowest column index. */
 enum { BPDC_TIE_HASH = 0, BPDC_TIE_LOWEST_INDEX = 1 };
 
+/* Check-node rule of BP (Sec. II.C names both): scaled min-sum,
+ * r = alpha * min over the other |q|, or product-sum,
+ * r = alpha * 2 atanh(prod over the other tanh(|q| / 2)) (alpha = 1 for the
+ * plain rule), each saturated at llr_sat and signed by the syndrome bit and
+ * the other signs.  Product-sum runs on the plain kernel family only. */
+enum { BPDC_RULE_MIN_SUM = 0, BPDC_RULE_PRODUCT_SUM = 1 };
+
 /* Kernel family of a plan. */
 enum {
   BPDC_KERNEL_AUTO = 0,  /* autotuner picks among the fused variants */
@@ -84,6 +91,7 @@ typedef struct {
   float tie_eps;             /* DC tie set: L_i >= L_max - tie_eps * max(1, |L_max|) (>= 0) */
   int32_t tie_break;         /* BPDC_TIE_* */
   uint64_t seed;             /* tie-break hash seed */
+  int32_t rule;              /* BPDC_RULE_* */
 } bpdc_params;
 
 typedef struct bpdc_code_s* bpdc_code; /* immutable after creation */

@@ -1,4 +1,4 @@
-"""MI355X (gfx950) BP+DC decoding: min-sum belief propagation + degeneracy cutting.
+"""MI355X (gfx950) BP+DC decoding: min-sum / product-sum belief propagation + degeneracy cutting.
 
 Thin Python binding of ``libbpdc.so`` (the C ABI in ``include/bpdc.h``).  The
 decoder itself runs in the library's HIP kernels; this package only marshals
@@ -8,8 +8,8 @@ the library has not been built.
 """
 from ._lib import (BpdcError, Params, Code, Plan, lib, lib_path, lane_precompile, weighted_bpdc,
                    KERNEL_AUTO, KERNEL_PLAIN, KERNEL_LANE, KERNEL_GROUP,
-                   PRIOR_CHANNEL, PRIOR_POSTERIOR, TIE_HASH, TIE_LOWEST_INDEX)
+                   PRIOR_CHANNEL, PRIOR_POSTERIOR, TIE_HASH, TIE_LOWEST_INDEX, RULE_MIN_SUM, RULE_PRODUCT_SUM)
 
 __all__ = ["BpdcError", "Params", "Code", "Plan", "lib", "lib_path", "lane_precompile", "weighted_bpdc",
            "KERNEL_AUTO", "KERNEL_PLAIN", "KERNEL_LANE", "KERNEL_GROUP",
-           "PRIOR_CHANNEL", "PRIOR_POSTERIOR", "TIE_HASH", "TIE_LOWEST_INDEX"]
+           "PRIOR_CHANNEL", "PRIOR_POSTERIOR", "TIE_HASH", "TIE_LOWEST_INDEX", "RULE_MIN_SUM", "RULE_PRODUCT_SUM"]

@@ -19,6 +19,7 @@ LIB = os.path.join(HERE, "libbpdc.so")
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_LANE, KERNEL_GROUP = 0, 1, 2, 3
 PRIOR_CHANNEL, PRIOR_POSTERIOR = 0, 1
 TIE_HASH, TIE_LOWEST_INDEX = 0, 1
+RULE_MIN_SUM, RULE_PRODUCT_SUM = 0, 1
 
 EXPORTS = [
     "bpdc_code_create", "bpdc_code_destroy", "bpdc_code_info", "bpdc_plan_create",
@@ -41,7 +42,7 @@ class _Csr(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("max_iter", C.c_int32 * 2), ("alpha", C.c_float), ("second_pass_prior", C.c_int32),
                 ("stop_on_converge", C.c_int32), ("llr_sat", C.c_float), ("tie_eps", C.c_float),
-                ("tie_break", C.c_int32), ("seed", C.c_uint64)]
+                ("tie_break", C.c_int32), ("seed", C.c_uint64), ("rule", C.c_int32)]
 
 
 _lib = None
@@ -118,6 +119,7 @@ class Params:
     tie_eps: float = 1e-3
     tie_break: int = TIE_HASH
     seed: int = 0
+    rule: int = RULE_MIN_SUM
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -129,6 +131,7 @@ class Params:
         p.tie_eps = self.tie_eps
         p.tie_break = int(self.tie_break)
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        p.rule = int(self.rule)
         return p
 
 

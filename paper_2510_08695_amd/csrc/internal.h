@@ -37,6 +37,7 @@ struct KParams {
   int stop;
   int tie_lowest;
   unsigned long long seed;
+  int rule;  // 0 scaled min-sum, 1 product-sum
 };
 
 // Output / input buffers of one single-code decode.

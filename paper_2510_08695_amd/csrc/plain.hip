@@ -67,17 +67,46 @@ __global__ void k_init_msgs(DevCode c, PlainWs w, int64_t B, int pass, float lsa
   for (int k = c.h_col_ptr[v]; k < c.h_col_ptr[v + 1]; ++k) w.q[(size_t)c.h_col_edge[k] * B + b] = q0;
 }
 
+// Check half, product-sum rule (Sec. II.C): r_{c->v} = sign * alpha *
+// 2 atanh(product over the other edges of tanh(|q| / 2)), the product taken
+// left to right in row order; the magnitude saturates at lsat (atanh(1) is
+// +inf).  Sign as for min-sum.  At most 32 edges per check (the code limit).
+__device__ void check_product_sum(const DevCode& c, const PlainWs& w, int64_t B, int64_t b, int e0, int e1,
+                                  u32 neg, float alpha, float lsat) {
+  float th[32];
+  for (int e = e0; e < e1; ++e) {
+    const float q = w.q[(size_t)e * B + b];
+    neg ^= (q < 0.0f) ? 1u : 0u;
+    th[e - e0] = tanhf(fabsf(q) * 0.5f);
+  }
+  for (int e = e0; e < e1; ++e) {
+    float prod = 1.0f;
+    for (int o = e0; o < e1; ++o)
+      if (o != e) prod = prod * th[o - e0];
+    float mag = 2.0f * atanhf(prod);
+    if (!(mag < lsat)) mag = lsat;
+    const float val = alpha * mag;
+    const float q = w.q[(size_t)e * B + b];
+    const bool negative = (neg ^ ((q < 0.0f) ? 1u : 0u)) != 0u;
+    w.r[(size_t)e * B + b] = negative ? -val : val;
+  }
+}
+
 // Check half: r_{c->v} = sign * alpha * (min over the other |q|), sign =
 // s_c xor the other signs.  Minimum and second minimum start at lsat (a
 // minimum over no inputs is lsat) and are tracked with strict '<'.
 __global__ void k_check(DevCode c, PlainWs w, const uint64_t* syn, int sw64, int64_t B, int pass,
-                        float alpha, float lsat) {
+                        float alpha, float lsat, int rule) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int chk = blockIdx.y;
   if (b >= B) return;
   if (w.st[b] != (pass ? ST_PASS2 : ST_PASS1)) return;
   const int e0 = c.h_row_ptr[chk], e1 = c.h_row_ptr[chk + 1];
   u32 neg = syn_bit(syn, sw64, b, chk);
+  if (rule) {
+    check_product_sum(c, w, B, b, e0, e1, neg, alpha, lsat);
+    return;
+  }
   float m1 = lsat, m2 = lsat;
   int amin = -1;
   for (int e = e0; e < e1; ++e) {
@@ -236,7 +265,7 @@ hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, 
     hipLaunchKernelGGL(k_init_msgs, dim3(gx, c.n), blk, 0, stream, c, w, B, pass, p.lsat);
     for (int t = 1; t <= T; ++t) {
       hipLaunchKernelGGL(k_check, dim3(gx, c.m), blk, 0, stream, c, w, io.syn, sw64, B, pass, p.alpha,
-                         p.lsat);
+                         p.lsat, p.rule);
       hipLaunchKernelGGL(k_var, dim3(gx, c.n), blk, 0, stream, c, w, B, pass, p.lsat);
       hipLaunchKernelGGL(k_stop, dim3(gx), blk, 0, stream, c, w, io.syn, sw64, B, pass, t, T, p.stop);
     }

@@ -717,6 +717,10 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   if (!std::isfinite(P.alpha)) return fail(BPDC_ERR_INVALID_ARG, "alpha must be finite");
   if (P.second_pass_prior != BPDC_PRIOR_CHANNEL && P.second_pass_prior != BPDC_PRIOR_POSTERIOR)
     return fail(BPDC_ERR_INVALID_ARG, "bad second_pass_prior");
+  if (P.rule != BPDC_RULE_MIN_SUM && P.rule != BPDC_RULE_PRODUCT_SUM)
+    return fail(BPDC_ERR_INVALID_ARG, "bad rule");
+  if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel != BPDC_KERNEL_PLAIN && kernel != BPDC_KERNEL_AUTO)
+    return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain kernel family only");
   if (P.tie_break != BPDC_TIE_HASH && P.tie_break != BPDC_TIE_LOWEST_INDEX)
     return fail(BPDC_ERR_INVALID_ARG, "bad tie_break");
   if (kernel < BPDC_KERNEL_AUTO || kernel > BPDC_KERNEL_GROUP) return fail(BPDC_ERR_INVALID_ARG, "bad kernel");
@@ -732,6 +736,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   p->kp.stop = P.stop_on_converge != 0;
   p->kp.tie_lowest = P.tie_break == BPDC_TIE_LOWEST_INDEX;
   p->kp.seed = P.seed;
+  p->kp.rule = P.rule;
   HIP_TRY(hipGetDevice(&p->device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
@@ -749,7 +754,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   for (int i = 0; i < ncodes; ++i) {
     CodePlan& cp = p->per_code[i];
     bpdc_code c = codes[i];
-    if (kernel == BPDC_KERNEL_PLAIN) {
+    if (kernel == BPDC_KERNEL_PLAIN || p->kp.rule == BPDC_RULE_PRODUCT_SUM) {
       cp.kernel = BPDC_KERNEL_PLAIN;
       continue;
     }
@@ -800,6 +805,10 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     if (lds > (size_t)p->max_lds) {
       p->multi_ok = false;
       p->multi_why = "largest per-shot state exceeds the LDS of one workgroup";
+    }
+    if (p->kp.rule != BPDC_RULE_MIN_SUM) {
+      p->multi_ok = false;
+      p->multi_why = "the multi-code launch runs scaled min-sum only";
     }
     if (p->multi_ok) {
       bpdc::GroupTile t;
@@ -978,6 +987,7 @@ static bpdc_status wms_check(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
   if (K < 1) return fail(BPDC_ERR_INVALID_ARG, "ckpt_every must be >= 1");
   if (p->kp.second_pass_posterior)
     return fail(BPDC_ERR_UNSUPPORTED, "weighted min-sum supports the channel second-pass prior only");
+  if (p->kp.rule != BPDC_RULE_MIN_SUM) return fail(BPDC_ERR_UNSUPPORTED, "weighted decoding is min-sum only");
   const bpdc::DevCode& d = p->codes[code]->dev;
   if (bpdc::wms_backward_lds(d, K) > (size_t)p->max_lds || bpdc::wms_forward_lds(d) > (size_t)p->max_lds)
     return fail(BPDC_ERR_UNSUPPORTED, "code too large for the weighted min-sum kernels (LDS)");

@@ -10,6 +10,7 @@ decodes.
 Constructions (paper sections in brackets):
   * toric code of size L as the hypergraph product of the length-L cyclic
     repetition code [Sec. II.B, Kitaev's toric code];
+  * rotated surface code of odd distance d, [[d^2, 1, d]] [Sec. II.B];
   * bivariate bicycle codes H_X = (A|B), H_Z = (B^T|A^T) with x = S_l (x) I_m,
     y = I_l (x) S_m [Sec. II.B, Table I];
   * hypergraph products of random (3,4)-regular classical codes (a synthetic
@@ -150,6 +151,45 @@ def toric_code(L: int, p: float = 0.05, second_pass: str = "posterior") -> Code:
     c = hgp_code(repetition_cycle(L), name=f"toric{L}", p=p, second_pass=second_pass)
     c.meta.update({"family": "toric", "L": L})
     return c
+
+
+def rotated_surface_matrices(d: int):
+    """Rotated surface code of odd distance d on a d x d grid of data qubits.
+
+    Data qubit (r, c) is column r d + c.  Stabilisers sit on the faces (i, j),
+    0 <= i, j <= d, between qubits (i-1..i, j-1..j) that exist: X-type where
+    i + j is even, Z-type where it is odd; interior faces have weight 4, and
+    the weight-2 faces kept are the X-type ones on the top and bottom edges
+    (i = 0, d) and the Z-type ones on the left and right edges (j = 0, d).
+    Gives (d^2 - 1) / 2 stabilisers of each type and k = 1.
+    """
+    assert d >= 3 and d % 2 == 1
+    xs, zs = [], []
+    for i in range(d + 1):
+        for j in range(d + 1):
+            qs = [r * d + c for r in (i - 1, i) for c in (j - 1, j) if 0 <= r < d and 0 <= c < d]
+            xtype = (i + j) % 2 == 0
+            edge_tb = i in (0, d)
+            edge_lr = j in (0, d)
+            if len(qs) == 4 or (len(qs) == 2 and ((xtype and edge_tb) or (not xtype and edge_lr))):
+                (xs if xtype else zs).append(sorted(qs))
+
+    def mat(rows):
+        M = sp.lil_matrix((len(rows), d * d), dtype=np.int64)
+        for k, qs in enumerate(rows):
+            for q in qs:
+                M[k, q] = 1
+        return sp.csr_matrix(M)
+    return mat(xs), mat(zs)
+
+
+def rotated_surface_code(d: int, p: float = 0.01, second_pass: str = "posterior") -> Code:
+    """Rotated surface code [[d^2, 1, d]] [Sec. II.B]: H = H_Z (detects bit flips), D = H_X."""
+    from .f2 import logical_operators
+    HX, HZ = rotated_surface_matrices(d)
+    H, D = Csr.from_sparse(HZ), Csr.from_sparse(HX)
+    return Code(f"surface{d}", H, D, np.full(H.cols, p), logical_operators(D, H), second_pass,
+                {"family": "rotated_surface", "d": d})
 
 
 def bb_matrices(l: int, m: int, A_terms: Sequence[Tuple[str, int]],

@@ -13,7 +13,8 @@ def oracle_params(prm, second_pass: str) -> oracle.OracleParams:
     return oracle.OracleParams(max_iter1=prm.max_iter[0], max_iter2=prm.max_iter[1], alpha=prm.alpha,
                                second_pass_prior=second_pass, stop_on_converge=prm.stop_on_converge,
                                llr_sat=prm.llr_sat, tie_eps=prm.tie_eps,
-                               tie_break="lowest" if prm.tie_break == 1 else "hash", seed=prm.seed)
+                               tie_break="lowest" if prm.tie_break == 1 else "hash", seed=prm.seed,
+                               rule=getattr(prm, "rule", 0))
 
 
 def gpu_decode(plan, code, syndromes: np.ndarray, code_index: int = 0, shot_offset: int = 0,

@@ -152,6 +152,30 @@ def test_toric_and_hgp_parameters():
     assert not ((h.H.to_sparse() @ h.D.to_sparse().T).toarray() % 2).any()
 
 
+@pytest.mark.parametrize("d", [3, 5, 7])
+def test_rotated_surface_code_parameters(d):
+    """[[d^2, 1, d]] (Sec. II.B): (d^2 - 1) / 2 checks of each type, weights 2 and 4,
+    d - 1 weight-2 checks of each type, X and Z checks commute, k = 1."""
+    c = synth.rotated_surface_code(d)
+    assert (c.n, c.m, c.D.rows) == (d * d, (d * d - 1) // 2, (d * d - 1) // 2)
+    for M in (c.H, c.D):
+        w = np.asarray(M.row_weights())
+        assert set(w) == {2, 4} and (w == 2).sum() == d - 1
+    assert not ((c.H.to_dense().astype(int) @ c.D.to_dense().T.astype(int)) % 2).any()
+    assert c.n - synth.f2_rank(c.H) - synth.f2_rank(c.D) == 1 and c.O.shape[0] == 1
+    # the logical operator has weight >= d (a logical of weight < d would be an error
+    # the code cannot detect): check all words of weight < 3 for d = 3 by brute force
+    if d == 3:
+        import itertools
+        H = c.H.to_dense().astype(int)
+        for wt in (1, 2):
+            for sup in itertools.combinations(range(c.n), wt):
+                e = np.zeros((1, c.n), np.uint8)
+                e[0, list(sup)] = 1
+                if not ((H @ e[0]) % 2).any():
+                    assert not synth.residual_is_logical(e, c.O)[0]
+
+
 @pytest.mark.parametrize("final", [True, False])
 def test_phenomenological_dem_structure(final):
     base = synth.bb_code("bb72")
@@ -355,3 +379,28 @@ def test_bb144_first_pass_failure_and_flatness_match_tables_3_and_4():
     spread = np.stack([ph[:, r].max(1) - ph[:, r].min(1) for r in rows], axis=1)
     for eps_gap, frac in flat.items():
         assert abs((spread <= eps_gap).mean() - frac) < 0.08, eps_gap
+
+
+def test_surface49_first_pass_failure_matches_table_3():
+    """[[49,1,7]] rotated surface code, code capacity p = 0.01 (bit flips), product-sum BP
+    with T = n = 49 (Fig. 2 caption), posterior prior in the second pass (Sec. III.B).
+
+    Table III counts 11,995,211 first-pass failures in 1e8 shots (0.11995).  2e5 shots
+    give a binomial sd of 7.3e-4: the bound is 4 sd.  BP+DC then fails on 4.09e-4 of the
+    first-pass failures (3,098 + 1,810 of 11,995,211); on ~24,000 of them that is ~10
+    (Poisson), bounded loosely."""
+    g = {k: float(v) for k, v in _read_golden("paper_table3_surface49.txt")}
+    code = synth.rotated_surface_code(7, p=0.01)
+    B = 200_000
+    shots = synth.make_shots(code, B, 41)
+    out = oracle.decode(code, shots.syndromes,
+                        oracle.OracleParams(rule=oracle.PRODUCT_SUM, max_iter1=49, max_iter2=49, alpha=1.0,
+                                            second_pass_prior="posterior", seed=1),
+                        want_post=False)
+    dc = (out["flags"] & 2) != 0
+    rate = dc.mean()
+    sd = np.sqrt(g["bp_fail_per_shot"] * (1 - g["bp_fail_per_shot"]) / B)
+    assert abs(rate - g["bp_fail_per_shot"]) < 4 * sd, rate
+    fail = ((out["flags"] & 1) == 0) | synth.residual_is_logical(shots.errors ^ out["ehat"], code.O)
+    expect = g["bpdc_fail_given_bp_fail"] * dc.sum()
+    assert (fail & dc).sum() <= 3 * expect + 10
