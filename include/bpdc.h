@@ -61,7 +61,9 @@ enum { BPDC_TIE_HASH = 0, BPDC_TIE_LOWEST_INDEX = 1 };
  * r = alpha * min over the other |q|, or product-sum,
  * r = alpha * 2 atanh(prod over the other tanh(|q| / 2)) (alpha = 1 for the
  * plain rule), each saturated at llr_sat and signed by the syndrome bit and
- * the other signs.  Product-sum runs on the plain kernel family only. */
+ * the other signs.  Product-sum runs on the plain kernel family and, for codes
+ * of at most 96 edges, on the lane family (one lane per shot); not on the
+ * group family, the multi-code launch or weighted decoding. */
 enum { BPDC_RULE_MIN_SUM = 0, BPDC_RULE_PRODUCT_SUM = 1 };
 
 /* Kernel family of a plan. */
@@ -188,10 +190,11 @@ bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
  * kernel for (H, D) without touching a GPU (host-only; hipRTC).  The cache
  * directory is $BPDC_CACHE_DIR, else kcache/ beside libbpdc.so.  posterior =
  * 1 for plans with BPDC_PRIOR_POSTERIOR; uniform_prior = 1 for codes whose
- * priors are all equal (the kernel then takes the prior as one value).
- * BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
+ * priors are all equal (the kernel then takes the prior as one value); rule
+ * is the plan's BPDC_RULE_* (product-sum: one lane per shot, at most 96
+ * edges).  BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
 bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior,
-                                 int32_t uniform_prior);
+                                 int32_t uniform_prior, int32_t rule);
 
 const char* bpdc_status_string(bpdc_status status);
 const char* bpdc_last_error(void);

@@ -123,6 +123,15 @@ __device__ __forceinline__ float xchgf(float x) {
   return __uint_as_float(xchgu<J>(__float_as_uint(x)));
 }
 
+// Product-sum check output: the atanh of the leave-one-out product of
+// tanh(|q|/2), doubled and saturated (atanh(1) = +inf becomes lsat), scaled,
+// with the sign bit `neg`.
+__device__ __forceinline__ float ps_r(float prod, u32 neg, float alpha, float lsat) {
+  float mag = 2.0f * atanhf(prod);
+  mag = (mag < lsat) ? mag : lsat;
+  return __uint_as_float(__float_as_uint(alpha * mag) ^ (neg << 31));
+}
+
 // x of lane `src` (uniform across the wave) into scalar registers.
 __device__ __forceinline__ long long readlane64(long long x, int src) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, src);
@@ -152,6 +161,21 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 // ev), starting from the check's syndrome bit.
 #define NB_EP0(s, ev) ep_##s = (ev) ^ (S[(s) >> 5] << (31 - ((s) & 31)))
 #define NB_EP(s, ev) ep_##s ^= (ev)
+// Product-sum rule (NB_PS, one lane per shot): an edge's register R[k] takes
+// tanh(|q| / 2) once its column is swept, and the sign of q goes to bit b of
+// the check's sign word; at the check's last edge NB_PSR forms each new
+// r = sign * alpha * min(2 atanh(product of the other edges' values), lsat).
+#define NB_PSACC0(s, k, b, q)                                  \
+  {                                                            \
+    R[k] = tanhf(fabsf(q) * 0.5f);                             \
+    sb_##s = (__float_as_uint(q) >> 31) << (b);                \
+  }
+#define NB_PSACC(s, k, b, q)                                   \
+  {                                                            \
+    R[k] = tanhf(fabsf(q) * 0.5f);                             \
+    sb_##s |= (__float_as_uint(q) >> 31) << (b);               \
+  }
+#define NB_PSR(prod, neg) bpdc_lane::ps_r((prod), (neg), alpha, LS)
 // Complete slot s (degree d, field at bit `off` of W[cw]): r signs =
 // s_c xor parity of all q signs xor own sign; stop-test parity into U.  Only
 // bit 31 of ev, ep and U is meaningful: ep starts as the check's syndrome bit
@@ -262,8 +286,13 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
   const u64 below = (first == 0) ? 0ull : (~0ull >> (64 - first));
   const u64 leaders = NB_G == 4 ? 0x1111111111111111ull : (NB_G == 2 ? 0x5555555555555555ull : ~0ull);
 
+#if NB_PS
+  float R[NB_NR];  // per edge: r, or tanh(|q|/2) once its column is swept
+#else
   float A1[NB_SLOTS], A2[NB_SLOTS];
-  u32 W[NB_NWC], S[NB_SPW], C[NB_RC32];
+  u32 W[NB_NWC];
+#endif
+  u32 S[NB_SPW], C[NB_RC32];
   long long shot = -1;
   int t = 0, pass = 0, it1 = 0;
   bool want = true, dead = false;
@@ -332,6 +361,11 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
     // branch, so that the state keeps its registers
     const bool fresh = nshot >= 0;
     if (__ballot(fresh)) {
+#if NB_PS
+#pragma unroll
+      for (int k = 0; k < NB_NR; ++k) R[k] = fresh ? 0.0f : R[k];
+      const int tn = 0;
+#else
       float A1n[NB_SLOTS], A2n[NB_SLOTS];
       u32 Wn[NB_NWC];
       int tn;
@@ -358,6 +392,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       }
 #pragma unroll
       for (int w = 0; w < NB_NWC; ++w) W[w] = fresh ? Wn[w] : W[w];
+#endif
 #pragma unroll
       for (int w = 0; w < NB_SPW; ++w) S[w] = fresh ? nS[w] : S[w];
 #pragma unroll
@@ -492,6 +527,10 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
         }
       }
       // second pass from a zero check state (selects, as for new shots)
+#if NB_PS
+#pragma unroll
+      for (int k = 0; k < NB_NR; ++k) R[k] = to_dc ? 0.0f : R[k];
+#else
 #pragma unroll
       for (int s = 0; s < NB_SLOTS; ++s) {
         A1[s] = to_dc ? 0.0f : A1[s];
@@ -499,6 +538,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       }
 #pragma unroll
       for (int w = 0; w < NB_NWC; ++w) W[w] = to_dc ? 0u : W[w];
+#endif
       it1 = to_dc ? t : it1;
       pass = to_dc ? 1 : pass;
       t = to_dc ? -1 : t;

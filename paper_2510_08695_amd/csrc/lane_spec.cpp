@@ -154,11 +154,18 @@ void find_group(const HostGraph& g, int max_lanes, LaneGroup* out) {
   out->block = {blocks[0]};
 }
 
-bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::string* why) {
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, std::string* why) {
   auto fail = [&](const char* msg) {
     if (why) *why = msg;
     return false;
   };
+  if (rule) {
+    // product-sum: one lane per shot and one register per edge
+    max_lanes = 1;
+    size_t e = 0;
+    for (auto& r : g.rows) e += r.size();
+    if (e > 96) return fail("product-sum: more than 96 edges per lane");
+  }
   if (g.n > 1024) return fail("more than 1024 columns");
   if (g.m > 1024) return fail("more than 1024 checks");
   if (max_deg(g.rows) > 15) return fail("check degree above 15");
@@ -177,8 +184,9 @@ bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::strin
   return true;
 }
 
-LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes) {
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule) {
   const int n = g.n, m = g.m, md = (int)g.drows.size();
+  if (rule) max_lanes = 1;  // product-sum: one lane per shot
   LaneGroup grp;
   find_group(g, max_lanes, &grp);
   const int G = grp.lanes;
@@ -261,7 +269,8 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     << nslots << "\n#define NB_ROWS " << nrows << "\n#define NB_RC32 " << (nrows + 31) / 32 << "\n#define NB_NWC "
     << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1) << "\n#define NB_DMAXROW "
     << std::max(1, max_deg(g.drows)) << "\n#define NB_DUNIFORM " << (uniform_drows ? 1 : 0)
-    << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0) << "\n#define NB_G " << G;
+    << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0) << "\n#define NB_G " << G << "\n#define NB_PS "
+    << (rule ? 1 : 0);
   for (int k = 1; k < 4; ++k) o << "\n#define NB_LOFF" << k << " " << (k < G ? grp.off[k] : 0);
   o << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0) << "\n";
   // column -> (row << 2 | lane in group), for the cooperative DC code
@@ -295,6 +304,66 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     }
   o << "} while (0)\n";
 
+  if (rule) {
+    // Product-sum (one lane per shot): one register R[k] per edge, k running
+    // over the checks (slots) and, within a check, its columns in ascending
+    // order.  R[k] holds the edge's r until its column is swept, then
+    // tanh(|q| / 2); at the check's last edge the new r of every edge is
+    // formed from them (leave-one-out products left to right in column
+    // order, 2 atanh, saturation, sign) and written back.
+    std::vector<int> rbase(nslots + 1, 0);
+    for (int sl = 0; sl < nslots; ++sl) rbase[sl + 1] = rbase[sl] + (int)g.rows[slot_base[sl]].size();
+    o << "#define NB_NR " << std::max(1, rbase[nslots]) << "\n";
+    o << "#define NB_SWEEP() do { \\\n";
+    for (int sl = 0; sl < nslots; ++sl)
+      if (sdeg[sl]) o << "u32 sb_" << sl << ", ep_" << sl << "; \\\n";
+    for (int i : order) {
+      const auto& e = ev[i];
+      const int dv = (int)e.size();
+      o << "{ float L = NB_LAM(" << i << ", " << row_col[i] << "); \\\n";
+      std::vector<int> kk(dv), bb(dv);
+      for (int j = 0; j < dv; ++j) {
+        const auto& cols = g.rows[slot_base[e[j].slot]];
+        bb[j] = (int)(std::lower_bound(cols.begin(), cols.end(), row_col[i]) - cols.begin());
+        kk[j] = rbase[e[j].slot] + bb[j];
+        o << "const float r" << j << " = R[" << kk[j] << "]; \\\n";
+      }
+      for (int j = 0; j < dv; ++j) o << "L = L + r" << j << "; \\\n";  // ascending check order
+      o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
+      for (int j = 0; j < dv; ++j) {
+        const int sl = e[j].slot, d = (int)g.rows[slot_base[sl]].size();
+        o << "{ const float q = L - r" << j << "; " << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << sl << ", ev); "
+          << (pos[i][j] == 0 ? "NB_PSACC0(" : "NB_PSACC(") << sl << ", " << kk[j] << ", " << bb[j] << ", q); } \\\n";
+        if (pos[i][j] == sdeg[sl] - 1) {
+          // finalise check slot sl: d edges in registers rbase[sl] ..
+          const int k0 = rbase[sl];
+          o << "{ const u32 par_ = ((u32)__builtin_popcount(sb_" << sl << ") + (S[" << (sl >> 5) << "] >> " << (sl & 31)
+            << ")) & 1u; ";
+          for (int b = 0; b < d; ++b) o << "const float t" << b << "_ = R[" << k0 + b << "]; ";
+          for (int b = 0; b < d; ++b) {
+            std::string prod;
+            for (int x = 0; x < d; ++x) {
+              if (x == b) continue;
+              prod = prod.empty() ? "t" + std::to_string(x) + "_" : "(" + prod + ") * t" + std::to_string(x) + "_";
+            }
+            if (prod.empty()) prod = "1.0f";
+            o << "R[" << k0 + b << "] = NB_PSR(" << prod << ", par_ ^ ((sb_" << sl << " >> " << b << ") & 1u)); ";
+          }
+          o << "U |= ep_" << sl << "; } \\\n";
+        }
+      }
+      o << "} \\\n";
+    }
+    for (int sl = 0; sl < nslots; ++sl)
+      if (!sdeg[sl]) o << "U |= __builtin_amdgcn_ubfe(S[" << (sl >> 5) << "], " << (sl & 31) << ", 1) << 31; \\\n";
+    o << "} while (0)\n";
+    o << "#define NB_INIT1(W_, A1_, A2_, S_) do { } while (0)\n";
+    LaneSpec out;
+    out.src = o.str();
+    out.lanes = G;
+    out.spw = spw;
+    return out;
+  }
   o << "#define NB_SWEEP() do { \\\n";
   for (int s = 0; s < nslots; ++s)
     if (sdeg[s]) o << "float m1_" << s << ", m2_" << s << "; u32 am_" << s << ", sb_" << s << ", ep_" << s << "; \\\n";

@@ -40,7 +40,8 @@ struct LaneSpec {
 };
 
 void find_group(const HostGraph& g, int max_lanes, LaneGroup* out);
-bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, std::string* why);
-LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes);
+// rule: 0 scaled min-sum, 1 product-sum (one lane per shot, one register per edge)
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, std::string* why);
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule);
 
 }  // namespace bpdc

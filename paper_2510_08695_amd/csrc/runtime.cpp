@@ -313,12 +313,12 @@ bool uniform_prior(const bpdc_code_s* c) {
   return true;
 }
 
-bpdc_status build_lane(bpdc_code c, bool posterior, int num_cu, LaneKernel* lk) {
+bpdc_status build_lane(bpdc_code c, bool posterior, int rule, int num_cu, LaneKernel* lk) {
   std::string why;
-  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), &why))
+  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes());
+  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes(), rule);
   std::string src = spec.src;
   bpdc_status st = lane_code_object(src, &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
@@ -379,7 +379,7 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   // equal positive priors below the saturation level: the first iteration's
   // check state is the same for every shot up to the syndrome signs
   const float lam0 = c->lam[0];
-  a.skip0 = (uniform_prior(c) && lam0 > 0.0f && lam0 < p->kp.lsat && p->kp.T1 >= 1) ? 1 : 0;
+  a.skip0 = (p->kp.rule == 0 && uniform_prior(c) && lam0 > 0.0f && lam0 < p->kp.lsat && p->kp.T1 >= 1) ? 1 : 0;
   a.a1_init = p->kp.alpha * lam0;
   a.a2_init1 = p->kp.alpha * p->kp.lsat;
   void* args[] = {&a};
@@ -678,7 +678,9 @@ bpdc_status bpdc_code_info(bpdc_code c, int32_t* n, int32_t* m, int32_t* md, int
   return BPDC_OK;
 }
 
-bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior, int32_t uniform_prior) {
+bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior, int32_t uniform_prior,
+                                 int32_t rule) {
+  if (rule != BPDC_RULE_MIN_SUM && rule != BPDC_RULE_PRODUCT_SUM) return fail(BPDC_ERR_INVALID_ARG, "bad rule");
   std::string why;
   if (!H || !D || !csr_ok(H, &why) || !csr_ok(D, &why) || H->cols != D->cols)
     return fail(BPDC_ERR_INVALID_ARG, "bad CSR: %s", why.c_str());
@@ -695,11 +697,11 @@ bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t p
   g.drows.resize(D->rows);
   for (int r = 0; r < D->rows; ++r)
     for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
-  if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), &why))
+  if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), rule, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes()).src, &image,
-                          nullptr);
+  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes(), rule).src,
+                          &image, nullptr);
 }
 
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
@@ -719,8 +721,8 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     return fail(BPDC_ERR_INVALID_ARG, "bad second_pass_prior");
   if (P.rule != BPDC_RULE_MIN_SUM && P.rule != BPDC_RULE_PRODUCT_SUM)
     return fail(BPDC_ERR_INVALID_ARG, "bad rule");
-  if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel != BPDC_KERNEL_PLAIN && kernel != BPDC_KERNEL_AUTO)
-    return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain kernel family only");
+  if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_GROUP)
+    return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain and lane kernel families only");
   if (P.tie_break != BPDC_TIE_HASH && P.tie_break != BPDC_TIE_LOWEST_INDEX)
     return fail(BPDC_ERR_INVALID_ARG, "bad tie_break");
   if (kernel < BPDC_KERNEL_AUTO || kernel > BPDC_KERNEL_GROUP) return fail(BPDC_ERR_INVALID_ARG, "bad kernel");
@@ -754,15 +756,26 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   for (int i = 0; i < ncodes; ++i) {
     CodePlan& cp = p->per_code[i];
     bpdc_code c = codes[i];
-    if (kernel == BPDC_KERNEL_PLAIN || p->kp.rule == BPDC_RULE_PRODUCT_SUM) {
+    if (kernel == BPDC_KERNEL_PLAIN) {
       cp.kernel = BPDC_KERNEL_PLAIN;
       continue;
     }
+    const int rule = p->kp.rule;
     std::string why_lane, why_group;
-    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), &why_lane);
+    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why_lane);
+    if (rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_AUTO) {
+      // product-sum: the lane kernel when the code fits one lane, else plain
+      if (lane_ok) {
+        if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+        cp.kernel = BPDC_KERNEL_LANE;
+      } else {
+        cp.kernel = BPDC_KERNEL_PLAIN;
+      }
+      continue;
+    }
     const bool group_ok = group_fits(p.get(), c->dev, &why_group);
     if (kernel == BPDC_KERNEL_LANE) {
-      if ((st = build_lane(c, posterior, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
       continue;
     }
@@ -775,7 +788,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     // AUTO: the code-specialised lane kernel when the code fits one lane,
     // otherwise the autotuned group kernel
     if (lane_ok) {
-      if ((st = build_lane(c, posterior, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
     } else if (group_ok) {
       if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;

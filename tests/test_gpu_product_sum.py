@@ -1,6 +1,7 @@
 """Product-sum BP+DC on the GPU against the float64 oracle (needs an MI355X).
 
-The product-sum check rule (Sec. II.C; used by the paper for surface codes)
+The product-sum check rule (Sec. II.C; used by the paper for surface codes),
+on the plain kernel family and on the lane family (one lane per shot),
 evaluates tanh and atanh, whose float32 implementations on the GPU and in the
 host's C library may differ in the last bit; near a saturated product the
 difference is amplified, and on shots whose BP does not settle the float32
@@ -56,13 +57,22 @@ def _two_prop_ok(a, b, n):
     return abs(a - b) / n <= 4 * sd + 1.0 / n
 
 
+def _kernels(P, name):
+    # the lane family runs product-sum for codes of at most 96 edges (the surface codes here)
+    return [P.KERNEL_PLAIN] + ([P.KERNEL_LANE] if name.startswith("surface") else [])
+
+
+@pytest.mark.parametrize("kname", ["plain", "lane"])
 @pytest.mark.parametrize("name,p,shots,T", CASES)
-def test_product_sum_vs_float64_oracle(P, name, p, shots, T):
+def test_product_sum_vs_float64_oracle(P, kname, name, p, shots, T):
     code = _code(name, p)
+    kid = P.KERNEL_PLAIN if kname == "plain" else P.KERNEL_LANE
+    if kid not in _kernels(P, name):
+        pytest.skip("the lane family runs product-sum for codes of at most 96 edges")
     sh = synth.make_shots(code, shots, 5000 + shots)
     prm = P.Params(max_iter=(T, T), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=23,
                    rule=P.RULE_PRODUCT_SUM)
-    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_PLAIN)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
     g = gpu_decode(plan, code, sh.syndromes)
     ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "posterior"), precision="f64")
     # decisions on shots with clear margins
@@ -90,11 +100,30 @@ def test_product_sum_vs_float64_oracle(P, name, p, shots, T):
     np.testing.assert_array_equal(g["ehat"].astype(bool), g["post"] <= 0)
 
 
-def test_product_sum_plans(P):
-    code = synth.rotated_surface_code(5, p=0.03)
-    prm = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM)
+@pytest.mark.parametrize("name,p,shots,T", [c for c in CASES if c[0].startswith("surface")])
+def test_lane_product_sum_equals_plain_bit_for_bit(P, name, p, shots, T):
+    """The two GPU product-sum decoders evaluate tanh and atanh with the same device
+    math library, in the same order (leave-one-out products left to right in column
+    order, column sums in ascending check order): every output is identical."""
+    code = _code(name, p)
+    sh = synth.make_shots(code, shots, 6000 + shots)
+    prm = P.Params(max_iter=(T, T), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=29,
+                   rule=P.RULE_PRODUCT_SUM)
     c = P.Code.from_problem(code)
-    assert P.Plan([c], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
-    for k in (P.KERNEL_LANE, P.KERNEL_GROUP):
-        with pytest.raises(P.BpdcError):
-            P.Plan([c], prm, kernel=k)
+    a = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_PLAIN), code, sh.syndromes)
+    b = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_LANE), code, sh.syndromes)
+    for k in ("flags", "iters", "ehat", "cut"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
+
+
+def test_product_sum_plans(P):
+    prm = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM)
+    small = P.Code.from_problem(synth.rotated_surface_code(5, p=0.03))
+    assert P.Plan([small], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_LANE
+    big = P.Code.from_problem(synth.toric_code(6, p=0.05))  # 144 edges
+    assert P.Plan([big], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
+    with pytest.raises(P.BpdcError):
+        P.Plan([big], prm, kernel=P.KERNEL_LANE)
+    with pytest.raises(P.BpdcError):
+        P.Plan([small], prm, kernel=P.KERNEL_GROUP)
