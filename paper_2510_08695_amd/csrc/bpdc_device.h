@@ -75,6 +75,37 @@ __device__ __forceinline__ int dc_pick(const int* cols, const float* vals, int d
   return pick;
 }
 
+// Product-sum rule (Sec. II.C) in float32, written from the identities
+//   tanh(x/2) = (1 - e) / (1 + e),   e = exp(-x) = 2^(-x log2 e),
+//   2 atanh(p) = ln((1 + p) / (1 - p)) = ln 2 * log2((1 + p) / (1 - p)),
+// with the hardware exp2 / log2 / reciprocal (about 1 ulp each), and below
+// the points where those forms cancel (x < 1/2, p < 1/4) the odd Taylor
+// series of tanh(x/2) and of 2 atanh(p), whose first omitted terms are below
+// 1e-8 relative there.  Accurate to a few ulp, about 15 instructions each;
+// every GPU product-sum decoder uses these two functions.
+__device__ __forceinline__ float tanh_half(float x) {  // x >= 0
+  const float y = 0.5f * x, y2 = y * y;
+  float s = fmaf(y2, 62.0f / 2835.0f, -17.0f / 315.0f);
+  s = fmaf(s, y2, 2.0f / 15.0f);
+  s = fmaf(s, y2, -1.0f / 3.0f);
+  s = fmaf(s, y2, 1.0f);
+  const float series = y * s;
+  const float e = __builtin_amdgcn_exp2f(-fminf(x, 64.0f) * 1.44269504088896341f);
+  const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+  return x < 0.5f ? series : direct;
+}
+__device__ __forceinline__ float atanh2(float p) {  // 2 atanh(p), 0 <= p <= 1 (+inf at 1)
+  const float p2 = p * p;
+  float s = fmaf(p2, 1.0f / 11.0f, 1.0f / 9.0f);
+  s = fmaf(s, p2, 1.0f / 7.0f);
+  s = fmaf(s, p2, 1.0f / 5.0f);
+  s = fmaf(s, p2, 1.0f / 3.0f);
+  s = fmaf(s, p2, 1.0f);
+  const float series = 2.0f * p * s;
+  const float direct = __builtin_amdgcn_logf((1.0f + p) * __builtin_amdgcn_rcpf(1.0f - p)) * 0.693147180559945309f;
+  return p < 0.25f ? series : direct;
+}
+
 }  // namespace bpdc_dev
 
 #endif  // BPDC_DEVICE_H

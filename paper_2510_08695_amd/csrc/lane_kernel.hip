@@ -127,7 +127,7 @@ __device__ __forceinline__ float xchgf(float x) {
 // tanh(|q|/2), doubled and saturated (atanh(1) = +inf becomes lsat), scaled,
 // with the sign bit `neg`.
 __device__ __forceinline__ float ps_r(float prod, u32 neg, float alpha, float lsat) {
-  float mag = 2.0f * atanhf(prod);
+  float mag = bpdc_dev::atanh2(prod);
   mag = (mag < lsat) ? mag : lsat;
   return __uint_as_float(__float_as_uint(alpha * mag) ^ (neg << 31));
 }
@@ -167,12 +167,12 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 // r = sign * alpha * min(2 atanh(product of the other edges' values), lsat).
 #define NB_PSACC0(s, k, b, q)                                  \
   {                                                            \
-    R[k] = tanhf(fabsf(q) * 0.5f);                             \
+    R[k] = bpdc_dev::tanh_half(fabsf(q));                      \
     sb_##s = (__float_as_uint(q) >> 31) << (b);                \
   }
 #define NB_PSACC(s, k, b, q)                                   \
   {                                                            \
-    R[k] = tanhf(fabsf(q) * 0.5f);                             \
+    R[k] = bpdc_dev::tanh_half(fabsf(q));                      \
     sb_##s |= (__float_as_uint(q) >> 31) << (b);               \
   }
 #define NB_PSR(prod, neg) bpdc_lane::ps_r((prod), (neg), alpha, LS)

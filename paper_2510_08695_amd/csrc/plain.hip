@@ -71,19 +71,20 @@ __global__ void k_init_msgs(DevCode c, PlainWs w, int64_t B, int pass, float lsa
 // 2 atanh(product over the other edges of tanh(|q| / 2)), the product taken
 // left to right in row order; the magnitude saturates at lsat (atanh(1) is
 // +inf).  Sign as for min-sum.  At most 32 edges per check (the code limit).
+// tanh and atanh are bpdc_device.h's float32 forms, shared with the lane kernel.
 __device__ void check_product_sum(const DevCode& c, const PlainWs& w, int64_t B, int64_t b, int e0, int e1,
                                   u32 neg, float alpha, float lsat) {
   float th[32];
   for (int e = e0; e < e1; ++e) {
     const float q = w.q[(size_t)e * B + b];
     neg ^= (q < 0.0f) ? 1u : 0u;
-    th[e - e0] = tanhf(fabsf(q) * 0.5f);
+    th[e - e0] = bpdc_dev::tanh_half(fabsf(q));
   }
   for (int e = e0; e < e1; ++e) {
     float prod = 1.0f;
     for (int o = e0; o < e1; ++o)
       if (o != e) prod = prod * th[o - e0];
-    float mag = 2.0f * atanhf(prod);
+    float mag = bpdc_dev::atanh2(prod);
     if (!(mag < lsat)) mag = lsat;
     const float val = alpha * mag;
     const float q = w.q[(size_t)e * B + b];
