@@ -36,6 +36,7 @@ COUNTERS = {
     "bb144": (LANE_SOURCES, "profiles/bpdc_lane_kernel_bb144_p005_1e6_counters.md"),
     "phen": (GROUP_SOURCES, "profiles/k_group_phen_bb288_T18_p0003_1e5_counters.md"),
     "hgp64": (GROUP_SOURCES, "profiles/k_group_hgp64_counters.md"),
+    "surface7": (LANE_SOURCES, "profiles/bpdc_lane_kernel_surface7_ps_p001_1e6.md"),
 }
 
 
@@ -345,7 +346,7 @@ def run_surface7(args):
     B = args.shots
     res = _single(args, code, B, 7, prm, f"[[49,1,7]] rotated surface code, code capacity p=0.01, {B} shots, "
                   "product-sum, T=49+49, posterior second pass", "shots/s BP+DC product-sum surface d=7 p=0.01",
-                  P.KERNEL_LANE)
+                  P.KERNEL_LANE, traffic_key="surface7" if B == 1_000_000 else None)
     res["bp_fail_rate"] = res["dc_rate"]
     res["bp_fail_rate_paper"] = 11995211 / 1e8
     res["note"] = ("lane kernel, one lane per shot (the code has no translation symmetry); ops counted as 8 "
