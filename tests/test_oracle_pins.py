@@ -404,3 +404,22 @@ def test_surface49_first_pass_failure_matches_table_3():
     fail = ((out["flags"] & 1) == 0) | synth.residual_is_logical(shots.errors ^ out["ehat"], code.O)
     expect = g["bpdc_fail_given_bp_fail"] * dc.sum()
     assert (fail & dc).sum() <= 3 * expect + 10
+
+
+def test_surface49_flatness_matches_table_4():
+    """Table IV's surface-code row: the fraction of H_X rows with first-pass posterior
+    spread <= eps_gap on shots whose first BP step failed ([[49,1,7]], p = 0.01,
+    product-sum, T = n).  2e5 shots give ~24,000 failed shots and ~576,000 rows."""
+    flat = {float(a): float(b) for a, b in _read_golden("paper_table4_surface49.txt")}
+    code = synth.rotated_surface_code(7, p=0.01)
+    shots = synth.make_shots(code, 200_000, 43)
+    out = oracle.decode(code, shots.syndromes,
+                        oracle.OracleParams(rule=oracle.PRODUCT_SUM, max_iter1=49, max_iter2=49, alpha=1.0,
+                                            second_pass_prior="posterior", seed=1),
+                        want_post=False, want_post1=True)
+    dc = (out["flags"] & 2) != 0
+    ph = 1.0 / (1.0 + np.exp(out["post1"][dc].astype(np.float64)))
+    rows = [code.D.row(h) for h in range(code.D.rows)]
+    spread = np.stack([ph[:, r].max(1) - ph[:, r].min(1) for r in rows], axis=1)
+    for eps_gap, frac in flat.items():
+        assert abs((spread <= eps_gap).mean() - frac) < 0.01, eps_gap
