@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-diag", action="store_true", help="skip the untimed DC-diagnostics pass")
     ap.add_argument("--workload", default="bb144",
                     choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7"],
                     help="bb144: the headline configuration (default); the others are the "
@@ -177,6 +178,9 @@ def main():
                                                                                       8 * ((code.n + 63) // 64) + 1),
                           "launch_ms": launch_ms, "ops_per_launch": ops_per_step}
 
+    if not args.no_diag:
+        result["dc_diagnostics"] = _dc_diagnostics(plan, syn, code.n, 3, stream)
+
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -247,6 +251,42 @@ def _timed(fn, steps, stream):
     return a.elapsed_time(b) / steps
 
 
+def _golden_pairs(name):
+    """The paper's printed (key, value) pairs kept under tests/golden (each file cites its table)."""
+    out = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", name)):
+        line = line.split("#")[0].split()
+        if len(line) == 2:
+            out[line[0]] = float(line[1])
+    return out
+
+
+def _dc_diagnostics(plan, syn, n, steps, stream, paper_flat=None):
+    """DC diagnostics of one decode of the batch (spread histogram of the first-pass
+    posterior error probabilities over the rows of D, cut sizes), and the throughput
+    with the diagnostics switched on."""
+    import torch
+    st = torch.zeros(103 + n, dtype=torch.int64, device="cuda")
+    plan.set_dc_stats(st)
+    plan.decode(syn)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    ms = _timed(lambda: plan.decode(syn), steps, stream)
+    plan.set_dc_stats(None)
+    spread, n_dc, cuts = s[:101], int(s[101]), s[102:]
+    sizes = np.arange(cuts.size)
+    nz = np.nonzero(cuts)[0]
+    res = {"dc_shots": n_dc, "rows": int(spread.sum()),
+           "flat_fraction": {str(e): float(spread[:round(100 * e)].sum() / max(1, spread.sum()))
+                             for e in (0.1, 0.2, 0.3, 0.4, 0.5)},
+           "mean_cut": float((sizes * cuts).sum() / max(1, n_dc)),
+           "cut_range": [int(nz[0]), int(nz[-1])] if nz.size else None,
+           "ms_per_step_with_diagnostics": ms}
+    if paper_flat:
+        res["flat_fraction_paper"] = paper_flat
+    return res
+
+
 def _oracle_sample(code, syndromes, errors, op, seconds, chunk=2000):
     import oracle
     import synth
@@ -279,7 +319,7 @@ def _ler(code, errors, corr_words, flags):
     return k / len(flags), [lo, hi]
 
 
-def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None):
+def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None, paper_flat=None):
     import torch
     import paper_2510_08695_amd as P
     import synth
@@ -306,6 +346,8 @@ def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None
                         "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
                         "traffic": committed_traffic(traffic_key) if traffic_key else None,
                         "traffic_unit": "bytes per launch", "launch_ms": ms, "ops_per_launch": ops}}
+    if paper_flat is not None and not args.no_diag:
+        res["dc_diagnostics"] = _dc_diagnostics(plan, syn, code.n, 3, stream, paper_flat)
     if not args.no_plain and kernel != P.KERNEL_PLAIN:
         pplan = P.Plan([c], prm, kernel=P.KERNEL_PLAIN)
         pout = pplan.decode(syn)
@@ -346,7 +388,8 @@ def run_surface7(args):
     B = args.shots
     res = _single(args, code, B, 7, prm, f"[[49,1,7]] rotated surface code, code capacity p=0.01, {B} shots, "
                   "product-sum, T=49+49, posterior second pass", "shots/s BP+DC product-sum surface d=7 p=0.01",
-                  P.KERNEL_LANE, traffic_key="surface7" if B == 1_000_000 else None)
+                  P.KERNEL_LANE, traffic_key="surface7" if B == 1_000_000 else None,
+                  paper_flat=_golden_pairs("paper_table4_surface49.txt"))
     res["bp_fail_rate"] = res["dc_rate"]
     res["bp_fail_rate_paper"] = 11995211 / 1e8
     res["note"] = ("lane kernel, one lane per shot (the code has no translation symmetry); ops counted as 8 "

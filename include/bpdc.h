@@ -123,6 +123,22 @@ bpdc_status bpdc_plan_destroy(bpdc_plan plan);
 bpdc_status bpdc_plan_info(bpdc_plan plan, int32_t code, int32_t* kernel, int32_t* shots_per_wg,
                            int32_t* threads_per_wg);
 
+/* Diagnostics of degeneracy cutting (Appendix B: how flat are the posterior
+ * profiles DC picks from; how many columns it cuts).  While a buffer is set,
+ * every bpdc_decode of the plan adds, for each shot whose first pass failed,
+ * into d_stats (uint64 words on the plan's device, zeroed by the caller,
+ * updated with device atomics; the caller owns it):
+ *   [0, 101)     histogram over the rows h of D of the spread
+ *                Delta(h) = max - min of the first-pass posterior error
+ *                probabilities 1 / (1 + e^L) over the support of h, at bin
+ *                floor(100 Delta) (bin 100: Delta = 1);
+ *   [101]        number of shots that ran DC;
+ *   [102, 103+n) histogram of the cut size 0..n.
+ * words >= 103 + n of the decoded code (checked at decode time).  d_stats =
+ * NULL turns it off.  Lane and plain kernel families; decodes on the group
+ * family or the multi-code launch return BPDC_ERR_UNSUPPORTED while set. */
+bpdc_status bpdc_plan_set_dc_stats(bpdc_plan plan, uint64_t* d_stats, int64_t words);
+
 /* Device workspace (bytes) that bpdc_decode needs for a batch of B shots of
  * code `code` (bpdc_decode_multi: pass code = -1 and the total batch). */
 bpdc_status bpdc_workspace_size(bpdc_plan plan, int32_t code, int64_t B, size_t* bytes);

@@ -26,6 +26,7 @@ EXPORTS = [
     "bpdc_plan_destroy", "bpdc_plan_info", "bpdc_workspace_size", "bpdc_decode",
     "bpdc_decode_multi", "bpdc_graph_capture_multi", "bpdc_graph_launch",
     "bpdc_wms_ckpt_size", "bpdc_wms_forward", "bpdc_wms_backward", "bpdc_lane_precompile",
+    "bpdc_plan_set_dc_stats",
     "bpdc_status_string", "bpdc_last_error", "bpdc_version",
 ]
 
@@ -76,6 +77,7 @@ def lib():
             "bpdc_wms_forward": [P, I32, P, P, I64, I64, I32, P, P, P, P, C.c_size_t, P],
             "bpdc_wms_backward": [P, I32, P, P, I64, I32, P, P, P, P, C.c_size_t, P, P],
             "bpdc_lane_precompile": [C.POINTER(_Csr), C.POINTER(_Csr), I32, I32, I32],
+            "bpdc_plan_set_dc_stats": [P, P, I64],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -200,6 +202,19 @@ class Plan:
         k, s, t = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().bpdc_plan_info(self.handle, code, C.byref(k), C.byref(s), C.byref(t)))
         return {"kernel": k.value, "shots_per_wg": s.value, "threads": t.value}
+
+    def set_dc_stats(self, stats=None):
+        """Accumulate DC diagnostics of later decodes into `stats` (int64 tensor of at least
+        103 + n words on the GPU, zeroed by the caller), or stop (None).  Layout: [0, 101)
+        histogram of floor(100 * spread) of the first-pass posterior error probabilities over
+        each row of D on shots that ran DC, [101] number of such shots, [102, 103 + n) cut sizes."""
+        if stats is None:
+            _check(lib().bpdc_plan_set_dc_stats(self.handle, None, 0))
+            self._dc_stats = None
+            return
+        assert stats.is_cuda and stats.dtype.itemsize == 8 and stats.is_contiguous()
+        self._dc_stats = stats  # keep it alive while the plan writes to it
+        _check(lib().bpdc_plan_set_dc_stats(self.handle, _ptr(stats), stats.numel()))
 
     def workspace_size(self, code: int, B: int) -> int:
         n = C.c_size_t()

@@ -75,6 +75,25 @@ __device__ __forceinline__ int dc_pick(const int* cols, const float* vals, int d
   return pick;
 }
 
+// Degeneracy-cutting diagnostic (Appendix B): the spread of the posterior
+// error probabilities p = 1 / (1 + e^L) over a row of D (largest minus
+// smallest; p falls as L grows, so it is p(min L) - p(max L)), as a bin
+// floor(100 spread) in 0..100.  e^L by the hardware exp2 (about 1 ulp).
+template <int MAXD>
+__device__ __forceinline__ int spread_bin(const float* vals, int deg) {
+  float lo = vals[0], hi = vals[0];
+  for (int k = 1; k < MAXD; ++k)
+    if (k < deg) {
+      lo = fminf(lo, vals[k]);
+      hi = fmaxf(hi, vals[k]);
+    }
+  const float lg = 1.44269504088896341f;
+  const float plo = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(lo * lg));
+  const float phi = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(hi * lg));
+  const int bin = (int)((plo - phi) * 100.0f);
+  return bin < 0 ? 0 : (bin > 100 ? 100 : bin);
+}
+
 // Product-sum rule (Sec. II.C) in float32, written from the identities
 //   tanh(x/2) = (1 - e) / (1 + e),   e = exp(-x) = 2^(-x log2 e),
 //   2 atanh(p) = ln((1 + p) / (1 - p)) = ln 2 * log2((1 + p) / (1 - p)),

@@ -50,6 +50,7 @@ struct DecodeIO {
   float* post;
   uint64_t* cut;
   int16_t* iters;
+  uint64_t* dcstats;  // DC diagnostics (accumulated) or null
 };
 
 // Plain decoder: one launch per phase per iteration, edge-major state in HBM.

@@ -61,6 +61,7 @@ struct LaneArgs {
   float a1_init;                  // alpha * lambda: check state after a first iteration (equal priors)
   float a2_init1;                 // alpha * lsat: its second minimum for a check of degree 1
   int skip0;                      // start first passes from that state (equal priors, 0 < lambda < lsat)
+  unsigned long long* dcstats;    // DC diagnostics (NB_NSTAT words, accumulated) or null
 };
 
 // Posteriors in LDS as [column][shot slot of the wave], one slot per lane
@@ -68,6 +69,11 @@ struct LaneArgs {
 // group store with the same offsets).  The odd strides keep column-wise reads
 // free of bank conflicts.
 #define NB_LSTR (64 / NB_G + 1)
+// DC diagnostics (Appendix B): [0, 101) histogram of the spread of the
+// first-pass posterior error probabilities over each row of D on shots that
+// run DC, bin floor(100 spread); [101] number of such shots; [102, 103 + n)
+// histogram of the cut size.
+#define NB_NSTAT (103 + NB_N)
 #ifndef NB_CHUNK
 #define NB_CHUNK 16   // largest number of shots a wave claims at once
 #endif
@@ -241,6 +247,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
   __shared__ u32 sCut[NB_G][NB_RC32];
   __shared__ short sColRow[NB_N];
   __shared__ u32 sSyn[NB_CHUNK][NB_G * NB_SPW];  // staged syndrome words of the reservoir
+  __shared__ u32 sStat[NB_NSTAT];                 // this wave's DC diagnostics (when requested)
 #if !NB_UNIFORM_PRIOR
   __shared__ float sLamRow[NB_G][NB_ROWS];
 #endif
@@ -256,6 +263,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
 #endif
   }
   for (int i = lane; i < NB_N; i += 64) sColRow[i] = nb_col_row[i];
+  for (int i = lane; i < NB_NSTAT; i += 64) sStat[i] = 0u;
 #if !NB_UNIFORM_PRIOR
   for (int i = lane; i < NB_G * NB_ROWS; i += 64)
     sLamRow[i / NB_ROWS][i % NB_ROWS] = a.lam[nb_row_col[i / NB_ROWS][i % NB_ROWS]];
@@ -456,9 +464,11 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
 #else
             const int deg = sDdeg[h];
 #endif
-            if (deg > 0)
+            if (deg > 0) {
               pick[it] = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
                                                        (u64)(a.shot_offset + sshot), (u64)h);
+              if (a.dcstats) atomicAdd(&sStat[bpdc_dev::spread_bin<NB_DMAXROW>(vals, deg)], 1u);
+            }
           }
         }
         __syncthreads();
@@ -470,6 +480,12 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
           }
         }
         __syncthreads();
+        if (a.dcstats && lane == 0) {
+          int ncut = 0;
+          for (int w = 0; w < NB_G * NB_RC32; ++w) ncut += __popc(sCut[w / NB_RC32][w % NB_RC32]);
+          sStat[101] += 1u;
+          sStat[102 + ncut] += 1u;
+        }
 #if NB_POSTERIOR
         for (int u = lane; u < NB_N; u += 64) {
           const int cr = sColRow[u];
@@ -546,6 +562,11 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       want = want || finish;
     }
     t += 1;
+  }
+  if (a.dcstats) {
+    __syncthreads();
+    for (int i = lane; i < NB_NSTAT; i += 64)
+      if (sStat[i]) atomicAdd(&a.dcstats[i], (unsigned long long)sStat[i]);
   }
 }
 

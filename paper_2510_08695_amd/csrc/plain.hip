@@ -175,7 +175,7 @@ __global__ void k_stop(DevCode c, PlainWs w, const uint64_t* syn, int sw64, int6
 
 // Degeneracy cutting, one thread per shot whose first pass failed.
 __global__ void k_dc(DevCode c, PlainWs w, int64_t B, int64_t shot_offset, float lsat, float tie_eps,
-                     int tie_lowest, u64 seed, int posterior) {
+                     int tie_lowest, u64 seed, int posterior, unsigned long long* dcstats) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   if (w.st[b] != ST_NEED_DC) return;
@@ -194,6 +194,13 @@ __global__ void k_dc(DevCode c, PlainWs w, int64_t B, int64_t shot_offset, float
     const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, tie_eps, tie_lowest, seed,
                                            (u64)(shot_offset + b), (u64)h);
     w.lam2[(size_t)pick * B + b] = __builtin_huge_valf();
+    if (dcstats) atomicAdd(&dcstats[bpdc_dev::spread_bin<32>(vals, deg)], 1ull);
+  }
+  if (dcstats) {  // DC diagnostics: shots that ran DC, cut size
+    int ncut = 0;
+    for (int v = 0; v < c.n; ++v) ncut += w.lam2[(size_t)v * B + b] == __builtin_huge_valf() ? 1 : 0;
+    atomicAdd(&dcstats[101], 1ull);
+    atomicAdd(&dcstats[102 + ncut], 1ull);
   }
   w.st[b] = ST_PASS2;
 }
@@ -262,7 +269,7 @@ hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, 
     const int T = pass ? p.T2 : p.T1;
     if (pass == 1)
       hipLaunchKernelGGL(k_dc, dim3(gx), blk, 0, stream, c, w, B, io.shot_offset, p.lsat, p.tie_eps,
-                         p.tie_lowest, (u64)p.seed, p.second_pass_posterior);
+                         p.tie_lowest, (u64)p.seed, p.second_pass_posterior, (unsigned long long*)io.dcstats);
     hipLaunchKernelGGL(k_init_msgs, dim3(gx, c.n), blk, 0, stream, c, w, B, pass, p.lsat);
     for (int t = 1; t <= T; ++t) {
       hipLaunchKernelGGL(k_check, dim3(gx, c.m), blk, 0, stream, c, w, io.syn, sw64, B, pass, p.alpha,

@@ -268,6 +268,8 @@ struct bpdc_plan_s {
   bpdc::GroupTile multi_tile;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  uint64_t* dcstats = nullptr;  // DC diagnostics buffer (bpdc_plan_set_dc_stats) or null
+  int64_t dcstats_words = 0;
 };
 
 namespace {
@@ -298,6 +300,7 @@ struct LaneArgsHost {
   float a1_init;
   float a2_init1;
   int skip0;
+  unsigned long long* dcstats;
 };
 
 // Largest lane group the lane kernel may use for one shot (1, 2 or 4).
@@ -367,6 +370,7 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   a.d_row_ptr = c->dev.d_row_ptr;
   a.d_col = c->dev.d_col;
   a.queue = queue;
+  a.dcstats = (unsigned long long*)io.dcstats;
   a.alpha = p->kp.alpha;
   a.lsat = p->kp.lsat;
   a.tie_eps = p->kp.tie_eps;
@@ -844,6 +848,14 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   return BPDC_OK;
 }
 
+bpdc_status bpdc_plan_set_dc_stats(bpdc_plan p, uint64_t* d_stats, int64_t words) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (d_stats && words < 103) return fail(BPDC_ERR_INVALID_ARG, "DC diagnostics buffer too small");
+  p->dcstats = d_stats;
+  p->dcstats_words = d_stats ? words : 0;
+  return BPDC_OK;
+}
+
 bpdc_status bpdc_plan_destroy(bpdc_plan p) {
   if (!p) return BPDC_OK;
   for (auto& cp : p->per_code)
@@ -899,7 +911,13 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
   if (dev != p->device) return fail(BPDC_ERR_INVALID_ARG, "plan was created on device %d, current is %d", p->device, dev);
   const CodePlan& cp = p->per_code[code];
   bpdc_code c = p->codes[code];
-  bpdc::DecodeIO io{d_syn, B, shot_offset, d_corr, d_flags, d_post, d_cut, d_iters};
+  if (p->dcstats) {
+    if (cp.kernel == BPDC_KERNEL_GROUP)
+      return fail(BPDC_ERR_UNSUPPORTED, "DC diagnostics are kept by the lane and plain kernel families only");
+    if (p->dcstats_words < 103 + c->g.n)
+      return fail(BPDC_ERR_INVALID_ARG, "DC diagnostics buffer needs %d words", 103 + c->g.n);
+  }
+  bpdc::DecodeIO io{d_syn, B, shot_offset, d_corr, d_flags, d_post, d_cut, d_iters, p->dcstats};
   hipStream_t s = (hipStream_t)stream;
   switch (cp.kernel) {
     case BPDC_KERNEL_PLAIN:
@@ -930,6 +948,7 @@ bpdc_status bpdc_decode_multi(bpdc_plan p, const int32_t* d_code_of_shot, const 
   if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
     return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
+  if (p->dcstats) return fail(BPDC_ERR_UNSUPPORTED, "the multi-code launch keeps no DC diagnostics");
   if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
     return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
   return multi_enqueue(p, d_code_of_shot, d_syn, d_syn_off, d_corr, d_corr_off, d_flags, d_iters, B, shot_offset,
@@ -945,6 +964,7 @@ bpdc_status bpdc_graph_capture_multi(bpdc_plan p, const int32_t* d_code_of_shot,
   if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
     return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
+  if (p->dcstats) return fail(BPDC_ERR_UNSUPPORTED, "the multi-code launch keeps no DC diagnostics");
   if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
     return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
   hipStream_t s = (hipStream_t)stream;

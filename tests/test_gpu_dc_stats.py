@@ -1,0 +1,188 @@
+"""DC diagnostics on the GPU (needs an MI355X): the histograms bpdc_plan_set_dc_stats
+accumulates against the same statistics computed from the oracle's outputs.
+
+Appendix B measures how flat the first-pass posterior error probabilities are
+over each row of D on shots whose first BP step failed (Table IV: the fraction
+of rows with spread <= eps), and DC cuts one column per row of D.  The library
+bins the spread Delta(h) = max - min of 1 / (1 + e^L) over the support of row h
+at floor(100 Delta), counts the shots that ran DC and bins their cut sizes.
+
+Bars:
+  * min-sum (float32 oracle bit-exact with the GPU): number of DC shots and the
+    cut-size histogram equal the oracle's exactly; the spread histogram equals
+    the one binned from the oracle's first-pass posteriors in float64 except for
+    rows whose 100 Delta lies within 1e-3 of a bin edge (the GPU evaluates e^L
+    in float32: about 1e-6 in Delta), which may move by one bin;
+  * product-sum (float64 oracle; float32 trajectories of failing shots part
+    from it): DC shot count and cut-size histogram equal the GPU's own outputs
+    of the same call; the Table IV flatness fractions agree with the oracle's
+    on the same shots within 0.01, and at 1e6 shots with the paper's printed
+    row for [[49,1,7]] within 0.01.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import gpu_decode, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+NSPREAD = 101
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2510_08695_amd as P
+    P.lib()
+    return P
+
+
+def _stats_buffer(n):
+    import torch
+    return torch.zeros(NSPREAD + 2 + n, dtype=torch.int64, device="cuda")
+
+
+def _read_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split())
+    return rows
+
+
+def spread_from_post1(code, post1, dc):
+    """Delta(h) for every (DC shot, row of D with a nonempty support), float64."""
+    ph = 1.0 / (1.0 + np.exp(post1[dc].astype(np.float64)))
+    rows = [code.D.row(h) for h in range(code.D.rows)]
+    rows = [r for r in rows if len(r)]
+    return np.stack([ph[:, r].max(1) - ph[:, r].min(1) for r in rows], axis=1).reshape(-1)
+
+
+def spread_hist(spread):
+    return np.bincount(np.clip(np.floor(spread * 100.0), 0, 100).astype(np.int64), minlength=NSPREAD)
+
+
+def near_edge(spread, band=1e-3):
+    x = spread * 100.0
+    k = np.round(x)
+    return (np.abs(x - k) < band) & (k >= 1)
+
+
+def cut_hist(cut_rows, n):
+    return np.bincount(cut_rows.sum(1).astype(np.int64), minlength=n + 1)
+
+
+def flat_fractions(spread_bins, eps_list):
+    """Fraction of rows with Delta < eps from a spread histogram (bins floor(100 Delta))."""
+    tot = spread_bins.sum()
+    return {e: spread_bins[:int(round(100 * e))].sum() / tot for e in eps_list}
+
+
+@pytest.mark.parametrize("kernel", ["lane", "plain"])
+@pytest.mark.parametrize("name,p,shots,T", [("bb144", 0.05, 3000, (100, 100)), ("bb72", 0.06, 2000, (40, 40))])
+def test_min_sum_dc_stats_vs_float32_oracle(P, kernel, name, p, shots, T):
+    import torch
+    code = synth.bb_code(name, p=p)
+    sh = synth.make_shots(code, shots, 7000 + shots)
+    sp = P.PRIOR_POSTERIOR if code.second_pass == "posterior" else P.PRIOR_CHANNEL
+    prm = P.Params(max_iter=T, alpha=0.625, second_pass_prior=sp, seed=31)
+    kid = P.KERNEL_LANE if kernel == "lane" else P.KERNEL_PLAIN
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    st = _stats_buffer(code.n)
+    plan.set_dc_stats(st)
+    print(f"case {name} p={p} shots={shots} kernel={kernel}", flush=True)
+    g = gpu_decode(plan, code, sh.syndromes, shot_offset=3, want_post=False)
+    s = st.cpu().numpy()
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, code.second_pass), precision="f32",
+                        shot_offset=3, want_post=False, want_post1=True)
+    dc = (ref["flags"] & 2) != 0
+    assert dc.sum() > 20, "case must exercise DC"
+    np.testing.assert_array_equal(g["flags"], ref["flags"])
+    assert s[NSPREAD] == dc.sum()
+    np.testing.assert_array_equal(s[NSPREAD + 1:], cut_hist(ref["cut"][dc], code.n))
+    spread = spread_from_post1(code, ref["post1"], dc)
+    want = spread_hist(spread)
+    assert s[:NSPREAD].sum() == want.sum() == spread.size
+    amb = int(near_edge(spread).sum())
+    assert amb < 0.01 * spread.size
+    assert np.abs(s[:NSPREAD] - want).sum() <= 2 * amb, (amb, np.nonzero(s[:NSPREAD] - want))
+    # accumulation: a second call adds the same counts; switched off, nothing changes
+    gpu_decode(plan, code, sh.syndromes, shot_offset=3, want_post=False)
+    np.testing.assert_array_equal(st.cpu().numpy(), 2 * s)
+    plan.set_dc_stats(None)
+    gpu_decode(plan, code, sh.syndromes, shot_offset=3, want_post=False)
+    np.testing.assert_array_equal(st.cpu().numpy(), 2 * s)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kernel", ["lane", "plain"])
+def test_product_sum_dc_stats_surface49(P, kernel):
+    code = synth.rotated_surface_code(7, p=0.01)
+    B = 20000
+    sh = synth.make_shots(code, B, 7100)
+    prm = P.Params(max_iter=(49, 49), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=1,
+                   rule=P.RULE_PRODUCT_SUM)
+    kid = P.KERNEL_LANE if kernel == "lane" else P.KERNEL_PLAIN
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    st = _stats_buffer(code.n)
+    plan.set_dc_stats(st)
+    print(f"case surface7 product-sum kernel={kernel}", flush=True)
+    g = gpu_decode(plan, code, sh.syndromes, want_post=False)
+    s = st.cpu().numpy()
+    dcg = (g["flags"] & 2) != 0
+    assert s[NSPREAD] == dcg.sum()
+    np.testing.assert_array_equal(s[NSPREAD + 1:], cut_hist(g["cut"][dcg], code.n))
+    # every row of H_X has a nonempty support
+    assert s[:NSPREAD].sum() == dcg.sum() * code.D.rows
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "posterior"), precision="f64",
+                        want_post=False, want_post1=True)
+    dc = (ref["flags"] & 2) != 0
+    want = spread_hist(spread_from_post1(code, ref["post1"], dc))
+    eps = [0.1, 0.2, 0.3, 0.4, 0.5]
+    fg, fr = flat_fractions(s[:NSPREAD], eps), flat_fractions(want, eps)
+    for e in eps:
+        assert abs(fg[e] - fr[e]) < 0.01, (e, fg[e], fr[e])
+
+
+def test_product_sum_flatness_matches_table_4(P):
+    """Table IV's [[49,1,7]] row (p = 0.01, product-sum, T = n), measured by the lane
+    kernel's diagnostics over 1e6 shots (~120,000 failed first passes, ~2.9e6 rows)."""
+    flat = {float(a): float(b) for a, b in _read_golden("paper_table4_surface49.txt")}
+    code = synth.rotated_surface_code(7, p=0.01)
+    sh = synth.make_shots(code, 1_000_000, 7200)
+    prm = P.Params(max_iter=(49, 49), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=1,
+                   rule=P.RULE_PRODUCT_SUM)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
+    st = _stats_buffer(code.n)
+    plan.set_dc_stats(st)
+    gpu_decode(plan, code, sh.syndromes, want_post=False)
+    s = st.cpu().numpy()
+    f = flat_fractions(s[:NSPREAD], list(flat))
+    for e, frac in flat.items():
+        assert abs(f[e] - frac) < 0.01, (e, f[e], frac)
+    # Table III: first-pass failures per shot 0.11995 (1e6 shots: sd 3.2e-4)
+    assert abs(s[NSPREAD] / 1e6 - 0.11995211) < 2e-3
+
+
+def test_dc_stats_rejected_where_unsupported(P):
+    code = synth.bb_code("bb144", p=0.05)
+    prm = P.Params(max_iter=(20, 20), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1)
+    sh = synth.make_shots(code, 256, 7300)
+    small = _stats_buffer(code.n)[:NSPREAD + 2]
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
+    plan.set_dc_stats(small)
+    with pytest.raises(P.BpdcError):
+        gpu_decode(plan, code, sh.syndromes, want_post=False)
+    grp = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    grp.set_dc_stats(_stats_buffer(code.n))
+    with pytest.raises(P.BpdcError):
+        gpu_decode(grp, code, sh.syndromes, want_post=False)
+    grp.set_dc_stats(None)
+    gpu_decode(grp, code, sh.syndromes, want_post=False)
