@@ -37,6 +37,7 @@ COUNTERS = {
     "phen": (GROUP_SOURCES, "profiles/k_group_phen_bb288_T18_p0003_1e5_counters.md"),
     "hgp64": (GROUP_SOURCES, "profiles/k_group_hgp64_counters.md"),
     "surface7": (LANE_SOURCES, "profiles/bpdc_lane_kernel_surface7_ps_p001_1e6.md"),
+    "circuit": (GROUP_SOURCES, "profiles/k_group_circuit_bb144_T12_p0001_2e4.md"),
 }
 
 
@@ -91,7 +92,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-diag", action="store_true", help="skip the untimed DC-diagnostics pass")
     ap.add_argument("--workload", default="bb144",
-                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7"],
+                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit"],
                     help="bb144: the headline configuration (default); the others are the "
                          "secondary configurations, each printing its own JSON line")
     ap.add_argument("--dem-form", default="open", choices=["open", "paper"])
@@ -113,7 +114,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "bb144":
         {"toric6": run_toric6, "phen": run_phen, "hgp64": run_hgp64, "wms": run_wms,
-         "surface7": run_surface7}[args.workload](args)
+         "surface7": run_surface7, "circuit": run_circuit}[args.workload](args)
         return
     p, B = args.p, args.shots
     code = synth.bb_code("bb144", p=p)
@@ -319,7 +320,8 @@ def _ler(code, errors, corr_words, flags):
     return k / len(flags), [lo, hi]
 
 
-def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None, paper_flat=None):
+def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None, paper_flat=None,
+            cpu_chunk=2000):
     import torch
     import paper_2510_08695_amd as P
     import synth
@@ -357,7 +359,8 @@ def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None
                                                   torch.equal(pout["flags"], out["flags"]))}
     if not args.no_cpu:
         sp = "posterior" if prm.second_pass_prior == P.PRIOR_POSTERIOR else "channel"
-        cb = _oracle_sample(code, shots.syndromes, shots.errors, oracle_params(prm, sp), args.cpu_seconds)
+        cb = _oracle_sample(code, shots.syndromes, shots.errors, oracle_params(prm, sp), args.cpu_seconds,
+                            chunk=cpu_chunk)
         k = cb.pop("shots")
         cb["gpu_ler_on_sample"] = _ler(code, shots.errors[:k], out["corr"].cpu().numpy().view(np.uint64)[:k],
                                        flags[:k])[0]
@@ -395,6 +398,23 @@ def run_surface7(args):
     res["note"] = ("lane kernel, one lane per shot (the code has no translation symmetry); ops counted as 8 "
                    "per edge-iteration as for min-sum, although each edge-iteration also evaluates one tanh "
                    "and one atanh")
+    print(json.dumps(res), flush=True)
+
+
+def run_circuit(args):
+    """[[144,12,12]] under circuit-level noise (Sec. IV.D, Appendix C): the detector
+    check matrix of T = d = 12 noisy rounds plus a noiseless one (936 x 8784, rows of
+    35 edges), the w = 3 detector degeneracy matrix (9576 rows), priors aggregated from
+    the syndrome circuit at p = 0.001; min-sum alpha = 0.625 with 1000 + 1000
+    iterations (Fig. 5 caption), channel prior in the second pass."""
+    import paper_2510_08695_amd as P
+    import synth
+    code = synth.bb_circuit_dem("bb144", 12, 0.001)
+    prm = P.Params(max_iter=(1000, 1000), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1)
+    B = 20_000
+    res = _single(args, code, B, 2012, prm, f"BB[[144,12,12]] circuit-level p=0.001, T=12 rounds (DCM 936x8784, "
+                  f"w=3 DDM 9576 rows), {B} shots, alpha=0.625, T=1000+1000", "shots/s BP+DC circuit-level BB144",
+                  P.KERNEL_GROUP, traffic_key="circuit", cpu_chunk=100)
     print(json.dumps(res), flush=True)
 
 

@@ -103,8 +103,9 @@ typedef struct bpdc_plan_s* bpdc_plan; /* launch configuration for one or more c
  * (m' x n, same n) and per-column prior error probabilities h_priors[n], each
  * in (0, 1).  The prior LLRs log((1-p)/p) are evaluated in double and rounded
  * once to float.  Copies everything to the current device; synchronous.
- * Row degree of H is limited to 32, column degree of H to 16, row degree of D
- * to 32 (BPDC_ERR_UNSUPPORTED otherwise). */
+ * Row degree of H is limited to 64, column degree of H to 16, row degree of D
+ * to 32 (BPDC_ERR_UNSUPPORTED otherwise); the group kernel family runs rows
+ * of up to 58 edges, product-sum rows of up to 32. */
 bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double* h_priors,
                              bpdc_code* out);
 bpdc_status bpdc_code_destroy(bpdc_code code);

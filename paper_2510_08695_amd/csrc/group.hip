@@ -36,7 +36,7 @@ struct GCode {
   const int32_t* d_row_ptr;
   const int32_t* d_col;
   const float* lam;
-  const int32_t* v_ell;  // [max_col_deg][n]: (check << 5) | position in the check's row, ascending checks; -1 pad
+  const int32_t* v_ell;  // [max_col_deg][n]: (check << 6) | position in the check's row, ascending checks; -1 pad
   const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; -1 pad
   int max_col_deg, max_row_deg;
 };
@@ -64,24 +64,36 @@ struct GArgs {
   KParams p;
 };
 
-// Packed per-check info: low bits r-sign of each edge, top bits argmin position.
+// Packed per-check info: low bits r-sign of each edge, top bits argmin
+// position; 16 bits for rows of at most 12 edges, 32 for at most 27, 64 for
+// at most 58 (Word: the register type the kernel computes it in).
 template <class InfoT>
 struct InfoTraits;
 template <>
 struct InfoTraits<uint16_t> {
   static constexpr int kPosShift = 12;
+  using Word = u32;
 };
 template <>
 struct InfoTraits<u32> {
   static constexpr int kPosShift = 27;
+  using Word = u32;
 };
+template <>
+struct InfoTraits<u64> {
+  static constexpr int kPosShift = 58;
+  using Word = u64;
+};
+
+__device__ __forceinline__ int popc_word(u32 x) { return __builtin_popcount(x); }
+__device__ __forceinline__ int popc_word(u64 x) { return __builtin_popcountll(x); }
 
 // r of the edge at row position k from the packed check state: alpha*min2 on
 // the argmin edge, alpha*min1 elsewhere, sign bit k of the info word.
 template <class InfoT>
-__device__ __forceinline__ float decode_r2(float2 a12, u32 info, int k) {
+__device__ __forceinline__ float decode_r2(float2 a12, typename InfoTraits<InfoT>::Word info, int k) {
   const float mag = ((int)(info >> InfoTraits<InfoT>::kPosShift) == k) ? a12.y : a12.x;
-  return __uint_as_float(__float_as_uint(mag) ^ (((info >> k) & 1u) << 31));
+  return __uint_as_float(__float_as_uint(mag) ^ ((u32)((info >> k) & 1u) << 31));
 }
 
 // Load through a global-address-space pointer (the code tables are reached
@@ -100,6 +112,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
   const KParams& P = a.p;
   const float LS = P.lsat;
   const float INF = __builtin_huge_valf();
+  using W = typename InfoTraits<InfoT>::Word;
 
   for (;;) {
     if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
@@ -118,7 +131,9 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     u32* cutw = (u32*)(L + n);                     // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     float* lam2 = (float*)(synw + ((m + 31) >> 5));  // [n] (posterior second pass)
-    InfoT* info = (InfoT*)(lam2 + (P.second_pass_posterior ? n : 0));  // [m]
+    // [m], aligned to its size
+    InfoT* info = (InfoT*)(((uintptr_t)(lam2 + (P.second_pass_posterior ? n : 0)) + sizeof(InfoT) - 1) &
+                           ~(uintptr_t)(sizeof(InfoT) - 1));
 
     const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
     for (int w = tid; w < ((m + 31) >> 5); w += nt) {
@@ -152,16 +167,16 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
 #pragma unroll
               for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : -1;
               float2 aa[4];
-              u32 in[4];
+              W in[4];
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
-                const int c = (ent[j] >= 0 ? ent[j] : 0) >> 5;
+                const int c = (ent[j] >= 0 ? ent[j] : 0) >> 6;
                 aa[j] = A12[c];
-                in[j] = (u32)info[c];
+                in[j] = (W)info[c];
               }
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
-                const float r = decode_r2<InfoT>(aa[j], in[j], ent[j] & 31);
+                const float r = decode_r2<InfoT>(aa[j], in[j], ent[j] & 63);
                 const float s = Lv + r;
                 Lv = (ent[j] >= 0) ? s : Lv;
               }
@@ -178,10 +193,11 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
         int bad = 0;
         for (int c = tid; c < m; c += nt) {
           const float2 ao = A12[c];
-          const u32 io = (u32)info[c];
+          const W io = (W)info[c];
           float m1 = LS, m2 = LS;
           int amin = 0, d = 0;
-          u32 sb = 0, par = (synw[c >> 5] >> (c & 31)) & 1u;
+          W sb = 0;
+          u32 par = (synw[c >> 5] >> (c & 31)) & 1u;
           // columns in chunks of 8, all loads of a chunk issued before the
           // updates; padding entries (-1) contribute nothing
           for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
@@ -202,16 +218,16 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
               amin = (aq < m1) ? k : amin;
               m2 = __builtin_amdgcn_fmed3f(aq, m1, m2);
               m1 = fminf(aq, m1);
-              sb |= ((ok && q < 0.0f) ? 1u : 0u) << k;
+              sb |= (W)((ok && q < 0.0f) ? 1u : 0u) << k;
               d = ok ? k + 1 : d;
             }
             if (vv[7] < 0) break;
           }
           bad |= (int)par;
-          const u32 rp = ((u32)__builtin_popcount(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
-          const u32 rb = rp ? (sb ^ ((1u << d) - 1u)) : sb;
+          const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
+          const W rb = rp ? (sb ^ (((W)1 << d) - (W)1)) : sb;
           A12[c] = make_float2(P.alpha * m1, P.alpha * m2);
-          info[c] = (InfoT)(rb | ((u32)amin << InfoTraits<InfoT>::kPosShift));
+          info[c] = (InfoT)(rb | ((W)amin << InfoTraits<InfoT>::kPosShift));
         }
         if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
         __syncthreads();
@@ -305,16 +321,16 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 
 }  // namespace
 
-size_t group_lds_bytes_nm(int n, int m, bool posterior, bool info16) {
+size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes) {
   size_t words = (size_t)n + 2 * (size_t)m + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
-  return words * 4 + (size_t)m * (info16 ? 2 : 4) + 16;
+  return words * 4 + (size_t)m * info_bytes + 8 + 16;  // 8: alignment of the info array
 }
 
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
                         const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
-                        size_t lds, bool info16, unsigned long long* queue, hipStream_t stream) {
+                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream) {
   GArgs a;
   a.codes = (const GCode*)d_codes;
   a.code_of_shot = code_of_shot;
@@ -334,16 +350,17 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
   (void)hipGetLastError();  // report only this launch's errors
   hipError_t e = fill_u64((uint64_t*)queue, 0, 1, stream);
   if (e != hipSuccess) return e;
-  if (info16) hipLaunchKernelGGL(k_group<uint16_t>, dim3(grid), dim3(threads), lds, stream, a);
-  else hipLaunchKernelGGL(k_group<u32>, dim3(grid), dim3(threads), lds, stream, a);
+  if (info_bytes == 2) hipLaunchKernelGGL(k_group<uint16_t>, dim3(grid), dim3(threads), lds, stream, a);
+  else if (info_bytes == 4) hipLaunchKernelGGL(k_group<u32>, dim3(grid), dim3(threads), lds, stream, a);
+  else hipLaunchKernelGGL(k_group<u64>, dim3(grid), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
 // Allow the group kernels up to `max_lds` bytes of dynamic LDS (once per
 // process and device), then report how many workgroups of `threads` threads
 // and `lds` bytes fit on a compute unit.
-int group_occupancy(int threads, size_t lds, bool info16, int max_lds) {
-  // raise the dynamic-LDS limit of both instantiations once; a refusal leaves
+int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds) {
+  // raise the dynamic-LDS limit of the three instantiations once; a refusal leaves
   // the default limit (and its error is cleared so that it is not reported
   // by a later launch check)
   static int raised_to = -1;
@@ -351,13 +368,16 @@ int group_occupancy(int threads, size_t lds, bool info16, int max_lds) {
     if (hipFuncSetAttribute((const void*)k_group<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
             hipSuccess ||
         hipFuncSetAttribute((const void*)k_group<u32>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_group<u64>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
             hipSuccess)
       (void)hipGetLastError();
     raised_to = max_lds;
   }
   int nb = 0;
-  hipError_t e = info16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds);
+  hipError_t e = info_bytes == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds)
+                 : info_bytes == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds)
+                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u64>, threads, lds);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;

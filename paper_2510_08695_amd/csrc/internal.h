@@ -25,7 +25,7 @@ struct DevCode {
   int32_t* d_row_ptr = nullptr;  // [md+1]
   int32_t* d_col = nullptr;      // [dnnz]
   float* lam = nullptr;          // [n]
-  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 5 | position in row), ascending rows; -1 pad
+  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 6 | position in row), ascending rows; -1 pad
   int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; -1 pad
 };
 
@@ -64,18 +64,18 @@ struct GroupTile {
   int threads = 256;
   int grid = 0;          // persistent workgroups
   size_t lds_bytes = 0;  // dynamic LDS per workgroup
-  bool info16 = false;   // 16-bit per-check info (row degree <= 12)
+  int info_bytes = 4;    // per-check info word: 2 (row degree <= 12), 4 (<= 27) or 8 bytes (<= 58)
 };
 
 // Group decoder (group.hip): persistent fused kernel, one workgroup per shot,
 // the shot's state in dynamic LDS; also the multi-code launch.
-size_t group_lds_bytes_nm(int n, int m, bool posterior, bool info16);
-int group_occupancy(int threads, size_t lds, bool info16, int max_lds);
+size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes);
+int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds);
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
                         const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
-                        size_t lds, bool info16, unsigned long long* queue, hipStream_t stream);
+                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream);
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,
                        unsigned* hist, unsigned* base, int32_t* order, hipStream_t stream);
 

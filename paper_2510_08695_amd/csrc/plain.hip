@@ -70,7 +70,8 @@ __global__ void k_init_msgs(DevCode c, PlainWs w, int64_t B, int pass, float lsa
 // Check half, product-sum rule (Sec. II.C): r_{c->v} = sign * alpha *
 // 2 atanh(product over the other edges of tanh(|q| / 2)), the product taken
 // left to right in row order; the magnitude saturates at lsat (atanh(1) is
-// +inf).  Sign as for min-sum.  At most 32 edges per check (the code limit).
+// +inf).  Sign as for min-sum.  At most 32 edges per check (plan creation
+// refuses product-sum on longer rows).
 // tanh and atanh are bpdc_device.h's float32 forms, shared with the lane kernel.
 __device__ void check_product_sum(const DevCode& c, const PlainWs& w, int64_t B, int64_t b, int e0, int e1,
                                   u32 neg, float alpha, float lsat) {

@@ -395,14 +395,16 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
 
 // ---- group kernel: tile selection ---------------------------------------------------------
 
-bool code_info16(const bpdc::DevCode& d) { return d.max_row_deg <= 12; }
+// Bytes of the group kernel's packed per-check word: the r-sign bit of every
+// edge of the row and the argmin position.
+int code_info_bytes(const bpdc::DevCode& d) { return d.max_row_deg <= 12 ? 2 : (d.max_row_deg <= 27 ? 4 : 8); }
 
 bool group_fits(const bpdc_plan_s* p, const bpdc::DevCode& d, std::string* why) {
-  if (d.max_row_deg > 27) {
-    *why = "row degree above 27";
+  if (d.max_row_deg > 58) {
+    *why = "row degree above 58";
     return false;
   }
-  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, code_info16(d));
+  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, code_info_bytes(d));
   if (lds > (size_t)p->max_lds) {
     *why = "per-shot state of " + std::to_string(lds) + " bytes exceeds the LDS of one workgroup";
     return false;
@@ -456,7 +458,7 @@ float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, Tu
     (void)hipEventRecord(e0, 0);
     hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
                                       nullptr, nullptr, nullptr, S, 0, tile.threads, tile.grid, tile.lds_bytes,
-                                      tile.info16, tb.queue, 0);
+                                      tile.info_bytes, tb.queue, 0);
     (void)hipEventRecord(e1, 0);
     if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       best = -1.0f;
@@ -475,8 +477,8 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
                               float* best_ms_out) {
   const bpdc::DevCode& d = p->codes[code]->dev;
   bpdc::GroupTile base;
-  base.info16 = code_info16(d);
-  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, base.info16);
+  base.info_bytes = code_info_bytes(d);
+  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, base.info_bytes);
   std::vector<int> cands;
   for (int t : {64, 128, 256, 512, 1024}) {
     const int work = std::max(d.n, d.m);
@@ -486,7 +488,7 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   auto make = [&](int threads) {
     bpdc::GroupTile t = base;
     t.threads = threads;
-    const int nb = bpdc::group_occupancy(threads, t.lds_bytes, t.info16, p->max_lds);
+    const int nb = bpdc::group_occupancy(threads, t.lds_bytes, t.info_bytes, p->max_lds);
     t.grid = std::max(1, nb) * p->num_cu;
     return t;
   };
@@ -510,7 +512,7 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   float best = -1.0f;
   for (int th : cands) {
     bpdc::GroupTile t = make(th);
-    if (bpdc::group_occupancy(th, t.lds_bytes, t.info16, p->max_lds) < 1) continue;
+    if (bpdc::group_occupancy(th, t.lds_bytes, t.info_bytes, p->max_lds) < 1) continue;
     const float ms = time_group(p, code, t, tb, S);
     if (ms > 0 && (best < 0 || ms < best)) {
       best = ms;
@@ -559,7 +561,7 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
   HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, s));
   HIP_TRY(bpdc::group_launch(p->d_code_table, cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
                              nullptr, iters, B, shot_offset, p->multi_tile.threads, p->multi_tile.grid,
-                             p->multi_tile.lds_bytes, p->multi_tile.info16, queue, s));
+                             p->multi_tile.lds_bytes, p->multi_tile.info_bytes, queue, s));
   return BPDC_OK;
 }
 
@@ -618,7 +620,7 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
   for (auto& r : g.rows) d.max_row_deg = std::max(d.max_row_deg, (int)r.size());
   for (auto& r : g.cols) d.max_col_deg = std::max(d.max_col_deg, (int)r.size());
   for (auto& r : g.drows) d.max_drow_deg = std::max(d.max_drow_deg, (int)r.size());
-  if (d.max_row_deg > 32) return fail(BPDC_ERR_UNSUPPORTED, "H row degree %d above 32", d.max_row_deg);
+  if (d.max_row_deg > 64) return fail(BPDC_ERR_UNSUPPORTED, "H row degree %d above 64", d.max_row_deg);
   if (d.max_col_deg > 16) return fail(BPDC_ERR_UNSUPPORTED, "H column degree %d above 16", d.max_col_deg);
   if (d.max_drow_deg > 32) return fail(BPDC_ERR_UNSUPPORTED, "D row degree %d above 32", d.max_drow_deg);
   // prior LLR: log((1 - p) / p) in double, rounded once to float
@@ -644,7 +646,7 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
   for (int v = 0; v < g.n; ++v)
     for (int k = cp[v]; k < cp[v + 1]; ++k) {
       const int edge = ce[k], r = er[edge];
-      vell[(size_t)(k - cp[v]) * g.n + v] = (r << 5) | (edge - hrp[r]);
+      vell[(size_t)(k - cp[v]) * g.n + v] = (r << 6) | (edge - hrp[r]);
     }
   for (int r = 0; r < g.m; ++r)
     for (int k = hrp[r]; k < hrp[r + 1]; ++k) cell[(size_t)(k - hrp[r]) * g.m + r] = hci[k];
@@ -727,6 +729,11 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     return fail(BPDC_ERR_INVALID_ARG, "bad rule");
   if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_GROUP)
     return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain and lane kernel families only");
+  if (P.rule == BPDC_RULE_PRODUCT_SUM)
+    for (int i = 0; i < ncodes; ++i)
+      if (codes[i]->dev.max_row_deg > 32)
+        return fail(BPDC_ERR_UNSUPPORTED, "product-sum: code %d has a row of degree %d (at most 32)", i,
+                    codes[i]->dev.max_row_deg);
   if (P.tie_break != BPDC_TIE_HASH && P.tie_break != BPDC_TIE_LOWEST_INDEX)
     return fail(BPDC_ERR_INVALID_ARG, "bad tie_break");
   if (kernel < BPDC_KERNEL_AUTO || kernel > BPDC_KERNEL_GROUP) return fail(BPDC_ERR_INVALID_ARG, "bad kernel");
@@ -805,7 +812,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   // multi-code launch: the group kernel over all codes, LDS sized for the largest
   p->multi_ok = true;
   {
-    bool all16 = true;
+    int info_bytes = 2;
     size_t lds = 0;
     int maxw = 0;
     for (int i = 0; i < ncodes; ++i) {
@@ -814,11 +821,11 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
         p->multi_ok = false;
         p->multi_why = "code " + std::to_string(i) + ": " + why;
       }
-      all16 = all16 && code_info16(codes[i]->dev);
+      info_bytes = std::max(info_bytes, code_info_bytes(codes[i]->dev));
       maxw = std::max(maxw, std::max(codes[i]->dev.n, codes[i]->dev.m));
     }
     for (int i = 0; i < ncodes; ++i)
-      lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, posterior, all16));
+      lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, posterior, info_bytes));
     if (lds > (size_t)p->max_lds) {
       p->multi_ok = false;
       p->multi_why = "largest per-shot state exceeds the LDS of one workgroup";
@@ -829,7 +836,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     }
     if (p->multi_ok) {
       bpdc::GroupTile t;
-      t.info16 = all16;
+      t.info_bytes = info_bytes;
       t.lds_bytes = lds;
       int th = 64;
       while (th < 512 && th < maxw / 2) th *= 2;
@@ -839,7 +846,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
         if (codes[i]->dev.n > codes[big]->dev.n) big = i;
       if (p->per_code[big].kernel == BPDC_KERNEL_GROUP) th = p->per_code[big].tile.threads;
       t.threads = th;
-      const int nb = bpdc::group_occupancy(th, lds, all16, p->max_lds);
+      const int nb = bpdc::group_occupancy(th, lds, info_bytes, p->max_lds);
       t.grid = std::max(1, nb) * p->num_cu;
       p->multi_tile = t;
     }
@@ -929,7 +936,7 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
       const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
       HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
                                  d_cut, d_iters, B, shot_offset, cp.tile.threads, cp.tile.grid, cp.tile.lds_bytes,
-                                 cp.tile.info16, (unsigned long long*)d_ws, s));
+                                 cp.tile.info_bytes, (unsigned long long*)d_ws, s));
       return BPDC_OK;
     }
     default:

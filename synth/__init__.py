@@ -2,7 +2,7 @@
 
 This package builds the parity-check matrices of the codes the decoder is
 run on (toric, rotated surface, bivariate bicycle, hypergraph product, phenomenological
-detector error models) and draws seeded i.i.d. error patterns and their
+and circuit-level detector error models) and draws seeded i.i.d. error patterns and their
 syndromes.  It contains none of the decoder's arithmetic: no message
 passing, no degeneracy cutting.  Both the CPU oracle (``oracle/``) and the
 HIP library (``paper_2510_08695_amd``) consume what it produces, and neither
@@ -13,6 +13,7 @@ from .codes import (Csr, Code, toric_code, bb_code, hgp_code, random_regular_cla
                     rotated_surface_matrices)
 from .sample import (sample_errors, syndromes_of, pack_bits, unpack_bits, ShotSet, make_shots)
 from .f2 import f2_rank, logical_operators, residual_is_logical
+from .circuit import bb_circuit_dem, bb_circuit_matrices, bb_circuit_mechanisms
 
 __all__ = [
     "Csr", "Code", "toric_code", "bb_code", "hgp_code", "random_regular_classical",
@@ -20,4 +21,5 @@ __all__ = [
     "rotated_surface_matrices",
     "sample_errors", "syndromes_of", "pack_bits", "unpack_bits", "ShotSet", "make_shots",
     "f2_rank", "logical_operators", "residual_is_logical",
+    "bb_circuit_dem", "bb_circuit_matrices", "bb_circuit_mechanisms",
 ]
