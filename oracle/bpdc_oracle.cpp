@@ -41,6 +41,14 @@
 //  * the second pass starts from the channel prior (BB-type codes, Sec.
 //    III.B) or from the pass-1 posteriors (surface-type codes), with fresh
 //    messages.
+//  * intermittent soft DC (the extension Sec. V proposes, off by default):
+//    every soft_period iterations of the first pass, while H e != s, every
+//    row of D nominates as in DC (on the saturated posteriors of that
+//    iteration; the j-th application hashes row h as j * rows(D) + h) and
+//    the union of nominees has its prior error odds p / (1 - p) divided by
+//    e^soft_shift, i.e. its prior LLR raised by soft_shift; messages carry
+//    on.  The final DC and the second pass are unchanged (a channel second
+//    pass starts from the unshifted prior).
 //
 // Parity: pinned by the tests (tree-graph exact marginals and max-marginals,
 // single-check closed forms, brute-force maximum-likelihood bounds on tiny
@@ -68,6 +76,8 @@ struct OracleParams {
   double llr_sat;             // saturation magnitude (may be +inf)
   double tie_eps;             // relative tie tolerance for DC
   uint64_t seed;              // tie-break seed
+  int32_t soft_period;        // intermittent soft DC every soft_period pass-1 iterations (0 = off)
+  double soft_shift;          // prior-LLR increase of each soft nominee
 };
 
 }  // extern "C"
@@ -125,15 +135,52 @@ struct PassOut {
   double margin = INFINITY;         // smallest decision margin seen (instrumentation)
 };
 
-// One run of BP_decode on graph g.  `prior` is the prior LLR per column,
-// `frozen` marks columns held at prior probability 0, `w` holds one scale per
-// edge (CSR order) or is null (then every edge uses alpha).
+// Degeneracy cutting: one nominee per row of D (Alg. 1, the loop over rows).
+// Row h is hashed as row_base + h (0 for the DC between the passes).
 template <class Real>
-PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vector<Real>& prior,
+std::vector<unsigned char> degeneracy_cut(const Graph& D, int n, const std::vector<Real>& L1,
+                                          const OracleParams& prm, uint64_t shot, double* margin,
+                                          uint64_t row_base = 0) {
+  std::vector<unsigned char> cut(n, 0);
+  const Real eps = (Real)prm.tie_eps;
+  for (int h = 0; h < D.m; ++h) {
+    const int b = D.row_ptr[h], f = D.row_ptr[h + 1];
+    if (b == f) continue;
+    Real lmax = L1[D.col_idx[b]];
+    for (int e = b; e < f; ++e) lmax = std::max(lmax, L1[D.col_idx[e]]);
+    const Real scale = std::max((Real)1, (Real)std::fabs(lmax));
+    const Real thr = lmax - eps * scale;
+    std::vector<int> ties;
+    for (int e = b; e < f; ++e) {
+      const Real x = L1[D.col_idx[e]];
+      if (x >= thr) ties.push_back(D.col_idx[e]);
+      if (margin && x != lmax) *margin = std::min(*margin, (double)std::fabs(x - thr) / (double)scale);
+    }
+    int pick = ties[0];
+    if (prm.tie_break == 0) pick = ties[scale_draw(tie_hash(prm.seed, shot, row_base + (uint64_t)h), ties.size())];
+    cut[pick] = 1;
+  }
+  return cut;
+}
+
+// Intermittent soft DC inside a pass (off when null).
+struct SoftDC {
+  const Graph* D;
+  const OracleParams* prm;
+  uint64_t shot;
+};
+
+// One run of BP_decode on graph g.  `prior0` is the prior LLR per column,
+// `frozen` marks columns held at prior probability 0, `w` holds one scale per
+// edge (CSR order) or is null (then every edge uses alpha); `soft` turns on
+// intermittent soft DC.
+template <class Real>
+PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vector<Real>& prior0,
                         const std::vector<unsigned char>& frozen, const Real* w, Real alpha,
-                        int rule, int T, bool stop_on_converge, Real lsat) {
+                        int rule, int T, bool stop_on_converge, Real lsat, const SoftDC* soft = nullptr) {
   const int E = g.row_ptr[g.m];
   std::vector<Real> q(E), r(E), L(g.n);
+  std::vector<Real> prior = prior0;  // shifted by soft DC
   PassOut<Real> out;
   out.ehat.assign(g.n, 0);
   out.L.assign(g.n, 0);
@@ -209,6 +256,15 @@ PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vecto
     }
     out.iters = t;
     if (stop_on_converge && syndrome_ok()) break;
+    if (soft && t % soft->prm->soft_period == 0 && t < T && !syndrome_ok()) {
+      std::vector<Real> Ls(g.n);
+      for (int v = 0; v < g.n; ++v) Ls[v] = frozen[v] ? (Real)INFINITY : sat(L[v], lsat);
+      const uint64_t j = (uint64_t)(t / soft->prm->soft_period);
+      const std::vector<unsigned char> nom =
+          degeneracy_cut<Real>(*soft->D, g.n, Ls, *soft->prm, soft->shot, &out.margin, j * (uint64_t)soft->D->m);
+      for (int v = 0; v < g.n; ++v)
+        if (nom[v]) prior[v] = prior[v] + (Real)soft->prm->soft_shift;
+    }
   }
   out.converged = syndrome_ok();
   for (int v = 0; v < g.n; ++v) out.L[v] = frozen[v] ? (Real)INFINITY : sat(L[v], lsat);
@@ -224,32 +280,6 @@ struct ShotOut {
   double margin = INFINITY;
 };
 
-// Degeneracy cutting: one nominee per row of D (Alg. 1, the loop over rows).
-template <class Real>
-std::vector<unsigned char> degeneracy_cut(const Graph& D, int n, const std::vector<Real>& L1,
-                                          const OracleParams& prm, uint64_t shot, double* margin) {
-  std::vector<unsigned char> cut(n, 0);
-  const Real eps = (Real)prm.tie_eps;
-  for (int h = 0; h < D.m; ++h) {
-    const int b = D.row_ptr[h], f = D.row_ptr[h + 1];
-    if (b == f) continue;
-    Real lmax = L1[D.col_idx[b]];
-    for (int e = b; e < f; ++e) lmax = std::max(lmax, L1[D.col_idx[e]]);
-    const Real scale = std::max((Real)1, (Real)std::fabs(lmax));
-    const Real thr = lmax - eps * scale;
-    std::vector<int> ties;
-    for (int e = b; e < f; ++e) {
-      const Real x = L1[D.col_idx[e]];
-      if (x >= thr) ties.push_back(D.col_idx[e]);
-      if (margin && x != lmax) *margin = std::min(*margin, (double)std::fabs(x - thr) / (double)scale);
-    }
-    int pick = ties[0];
-    if (prm.tie_break == 0) pick = ties[scale_draw(tie_hash(prm.seed, shot, (uint64_t)h), ties.size())];
-    cut[pick] = 1;
-  }
-  return cut;
-}
-
 template <class Real>
 ShotOut<Real> decode_shot(const Graph& H, const Graph& D, const std::vector<Real>& lam,
                           const double* weights, const OracleParams& prm, const unsigned char* s,
@@ -264,8 +294,10 @@ ShotOut<Real> decode_shot(const Graph& H, const Graph& D, const std::vector<Real
   }
   ShotOut<Real> out;
   std::vector<unsigned char> none(n, 0);
+  const SoftDC soft{&D, &prm, shot};
   PassOut<Real> p1 = bp_decode<Real>(H, s, lam, none, weights ? w1.data() : nullptr, alpha, prm.rule,
-                                     prm.max_iter1, prm.stop_on_converge != 0, lsat);
+                                     prm.max_iter1, prm.stop_on_converge != 0, lsat,
+                                     prm.soft_period > 0 ? &soft : nullptr);
   out.iters[0] = p1.iters;
   out.L1 = p1.L;
   out.margin = p1.margin;

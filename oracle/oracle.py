@@ -40,7 +40,7 @@ class _Params(C.Structure):
                 ("second_pass_prior", C.c_int32), ("stop_on_converge", C.c_int32),
                 ("tie_break", C.c_int32), ("dc_form", C.c_int32), ("skip_dc", C.c_int32),
                 ("alpha", C.c_double), ("llr_sat", C.c_double), ("tie_eps", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("soft_period", C.c_int32), ("soft_shift", C.c_double)]
 
 
 @dataclass
@@ -57,6 +57,8 @@ class OracleParams:
     llr_sat: float = 64.0
     tie_eps: float = 1e-3
     seed: int = 0
+    soft_period: int = 0                   # intermittent soft DC every soft_period pass-1 iterations
+    soft_shift: float = 0.0                # prior-LLR increase of each soft nominee
 
     def to_c(self) -> _Params:
         return _Params(self.rule, self.max_iter1, self.max_iter2,
@@ -66,7 +68,7 @@ class OracleParams:
                        1 if self.dc_form == "delete_columns" else 0,
                        1 if self.skip_dc else 0,
                        float(self.alpha), float(self.llr_sat), float(self.tie_eps),
-                       int(self.seed) & 0xFFFFFFFFFFFFFFFF)
+                       int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.soft_period), float(self.soft_shift))
 
 
 _lib = None

@@ -423,3 +423,57 @@ def test_surface49_flatness_matches_table_4():
     spread = np.stack([ph[:, r].max(1) - ph[:, r].min(1) for r in rows], axis=1)
     for eps_gap, frac in flat.items():
         assert abs((spread <= eps_gap).mean() - frac) < 0.01, eps_gap
+
+
+# --------------------------------------------------------------------------------------
+# intermittent soft DC (the extension proposed in Sec. V; reading: every K pass-1
+# iterations while H e != s, the nominees' prior LLRs rise by beta)
+
+
+@pytest.mark.parametrize("K,beta", [(3, 2.0), (4, 0.5), (3, 0.3), (5, 0.75)])
+@pytest.mark.parametrize("seed", [1, 2, 3, 5, 8])
+def test_soft_dc_two_bit_closed_form(K, beta, seed):
+    """H = D = (1 1), s = 1, equal priors: scaled min-sum sits at the symmetric fixed
+    point L_0 = L_1 = (1 - alpha) lam and never converges.  The first soft application
+    (t = K) meets a tie and nominates the column v* drawn by the hash of row
+    rows(D) * 1 + 0; afterwards v* holds the larger posterior and is nominated again
+    at t = 2K, 3K, ....  After j applications the other column's posterior at iteration
+    jK + 2 is lam - alpha (lam + j beta), so BP converges at t = j* K + 2 with
+    j* = ceil(lam (1 - alpha) / (alpha beta)), flipping the column that was not nominated."""
+    p, alpha = 0.1, 0.625
+    lam = np.log((1 - p) / p)
+    code = synth.Code("two", Csr.from_dense([[1, 1]]), Csr.from_dense([[1, 1]]), np.full(2, p))
+    jstar = int(np.ceil(lam * (1 - alpha) / (alpha * beta)))
+    T1 = jstar * K + 10
+    prm = oracle.OracleParams(max_iter1=T1, max_iter2=5, alpha=alpha, seed=seed, soft_period=K,
+                              soft_shift=beta)
+    shots = np.ones((4, 1), np.uint8)
+    out = oracle.decode(code, shots, prm, precision="f64", shot_offset=17)
+    for b in range(4):
+        vstar = oracle.tie_hash(seed, 17 + b, 1) >> 63   # floor(h * 2 / 2^64)
+        assert out["flags"][b] == 1
+        assert out["iters"][b, 0] == jstar * K + 2
+        np.testing.assert_array_equal(out["ehat"][b], [1 - vstar == 0, 1 - vstar == 1])
+    # without soft DC the pass never converges and DC runs
+    base = oracle.decode(code, shots, oracle.OracleParams(max_iter1=T1, max_iter2=5, alpha=alpha, seed=seed),
+                         precision="f64")
+    assert (base["flags"] & 2).all() and (base["iters"][:, 0] == T1).all()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_soft_dc_reduces_to_bpdc(precision):
+    """beta = 0, or a period beyond the first pass, leaves BP+DC unchanged."""
+    code = synth.bb_code("bb72", p=0.06)
+    shots = synth.make_shots(code, 400, 77)
+    base = oracle.OracleParams(max_iter1=40, max_iter2=40, seed=3)
+    ref = oracle.decode(code, shots.syndromes, base, precision=precision, want_post1=True)
+    for soft in (dict(soft_period=4, soft_shift=0.0), dict(soft_period=40, soft_shift=3.0)):
+        o = oracle.decode(code, shots.syndromes, oracle.OracleParams(max_iter1=40, max_iter2=40, seed=3, **soft),
+                          precision=precision, want_post1=True)
+        for k in ("ehat", "flags", "iters", "cut", "post", "post1"):
+            np.testing.assert_array_equal(o[k], ref[k], err_msg=f"{soft} {k}")
+    # and a real shift changes the decoding of some shot
+    o = oracle.decode(code, shots.syndromes, oracle.OracleParams(max_iter1=40, max_iter2=40, seed=3,
+                                                                 soft_period=4, soft_shift=1.0),
+                      precision=precision)
+    assert (o["iters"] != ref["iters"]).any()
