@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-diag", action="store_true", help="skip the untimed DC-diagnostics pass")
     ap.add_argument("--workload", default="bb144",
-                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit"],
+                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit", "soft"],
                     help="bb144: the headline configuration (default); the others are the "
                          "secondary configurations, each printing its own JSON line")
     ap.add_argument("--dem-form", default="open", choices=["open", "paper"])
@@ -114,7 +114,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "bb144":
         {"toric6": run_toric6, "phen": run_phen, "hgp64": run_hgp64, "wms": run_wms,
-         "surface7": run_surface7, "circuit": run_circuit}[args.workload](args)
+         "surface7": run_surface7, "circuit": run_circuit, "soft": run_soft}[args.workload](args)
         return
     p, B = args.p, args.shots
     code = synth.bb_code("bb144", p=p)
@@ -415,6 +415,40 @@ def run_circuit(args):
     res = _single(args, code, B, 2012, prm, f"BB[[144,12,12]] circuit-level p=0.001, T=12 rounds (DCM 936x8784, "
                   f"w=3 DDM 9576 rows), {B} shots, alpha=0.625, T=1000+1000", "shots/s BP+DC circuit-level BB144",
                   P.KERNEL_GROUP, traffic_key="circuit", cpu_chunk=100)
+    print(json.dumps(res), flush=True)
+
+
+def run_soft(args):
+    """Intermittent soft DC (the extension Sec. V proposes) on the headline problem:
+    BB[[144,12,12]], p = 0.05, 1e6 shots, min-sum alpha = 0.625, T = 100 + 100, channel
+    second-pass prior; every 5 first-pass iterations the DC nominees' prior LLRs rise by
+    0.5.  Group kernel (the lane kernel has no soft DC); the same shots decoded without
+    soft DC by the headline lane kernel give the logical error rate it is compared with."""
+    import torch
+    import paper_2510_08695_amd as P
+    import synth
+    code = synth.bb_code("bb144", p=0.05)
+    B = args.shots
+    prm = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1,
+                   soft_period=5, soft_shift=0.5)
+    seed = 2005
+    res = _single(args, code, B, seed, prm, f"BB[[144,12,12]] code capacity p=0.05, {B} shots, min-sum alpha=0.625, "
+                  "T=100+100, soft DC every 5 iterations with prior-LLR shift 0.5", "shots/s BP+soft DC, BB144 p=0.05",
+                  P.KERNEL_GROUP, traffic_key=None)
+    shots = synth.make_shots(code, B, seed)
+    syn = torch.from_numpy(synth.pack_bits(shots.syndromes).view(np.int64)).cuda()
+    stream = torch.cuda.current_stream()
+    base = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1)
+    for name, kid in (("lane", P.KERNEL_LANE), ("group", P.KERNEL_GROUP)):
+        plan = P.Plan([P.Code.from_problem(code)], base, kernel=kid)
+        out = plan.decode(syn, want_iters=True)
+        ms = _timed(lambda: plan.decode(syn, out=out), max(1, args.steps // 2), stream)
+        flags = out["flags"].cpu().numpy()
+        ler, ci = _ler(code, shots.errors, out["corr"].cpu().numpy().view(np.uint64), flags)
+        res[f"without_soft_{name}"] = {"shots_per_s": B / (ms / 1e3), "ler": ler, "ler_ci95": ci,
+                                       "dc_rate": float(((flags & 2) != 0).mean()),
+                                       "mean_iters": float(out["iters"].cpu().numpy().astype(np.int64).sum()) / B}
+        del plan
     print(json.dumps(res), flush=True)
 
 

@@ -94,6 +94,19 @@ typedef struct {
   int32_t tie_break;         /* BPDC_TIE_* */
   uint64_t seed;             /* tie-break hash seed */
   int32_t rule;              /* BPDC_RULE_* */
+  /* Intermittent soft DC (the extension Sec. V proposes; 0 = off): every
+   * soft_period iterations of the first pass (t = K, 2K, ... < T1), on every
+   * shot whose H e != s, each row of D nominates as in DC on the saturated
+   * posteriors of that iteration (the j-th application hashes row h as
+   * j * rows(D) + h), and every nominee's prior LLR rises by soft_shift
+   * (>= 0, finite), i.e. its prior error odds p / (1 - p) shrink by the factor
+   * e^-soft_shift; messages carry on.  The DC after a failed first pass and
+   * the second pass are unchanged (the channel second-pass prior is the
+   * unshifted one).  Group and plain kernel families only (the lane family
+   * and weighted decoding return BPDC_ERR_UNSUPPORTED); AUTO picks the group
+   * family, or plain when a shot does not fit one workgroup. */
+  int32_t soft_period;
+  float soft_shift;
 } bpdc_params;
 
 typedef struct bpdc_code_s* bpdc_code; /* immutable after creation */

@@ -43,7 +43,8 @@ class _Csr(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("max_iter", C.c_int32 * 2), ("alpha", C.c_float), ("second_pass_prior", C.c_int32),
                 ("stop_on_converge", C.c_int32), ("llr_sat", C.c_float), ("tie_eps", C.c_float),
-                ("tie_break", C.c_int32), ("seed", C.c_uint64), ("rule", C.c_int32)]
+                ("tie_break", C.c_int32), ("seed", C.c_uint64), ("rule", C.c_int32),
+                ("soft_period", C.c_int32), ("soft_shift", C.c_float)]
 
 
 _lib = None
@@ -122,6 +123,8 @@ class Params:
     tie_break: int = TIE_HASH
     seed: int = 0
     rule: int = RULE_MIN_SUM
+    soft_period: int = 0      # intermittent soft DC every soft_period first-pass iterations (0: off)
+    soft_shift: float = 0.0   # prior-LLR increase of each soft nominee
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -134,6 +137,8 @@ class Params:
         p.tie_break = int(self.tie_break)
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.rule = int(self.rule)
+        p.soft_period = int(self.soft_period)
+        p.soft_shift = float(self.soft_shift)
         return p
 
 

@@ -130,9 +130,12 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     float* L = (float*)(A12 + m);                  // [n]
     u32* cutw = (u32*)(L + n);                     // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
-    float* lam2 = (float*)(synw + ((m + 31) >> 5));  // [n] (posterior second pass)
+    // [n] per-shot prior: the first pass's under soft DC, the second pass's
+    // with the posterior prior
+    float* lam2 = (float*)(synw + ((m + 31) >> 5));
+    const bool soft = P.soft_period > 0;
     // [m], aligned to its size
-    InfoT* info = (InfoT*)(((uintptr_t)(lam2 + (P.second_pass_posterior ? n : 0)) + sizeof(InfoT) - 1) &
+    InfoT* info = (InfoT*)(((uintptr_t)(lam2 + ((P.second_pass_posterior || soft) ? n : 0)) + sizeof(InfoT) - 1) &
                            ~(uintptr_t)(sizeof(InfoT) - 1));
 
     const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
@@ -146,11 +149,13 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     bool conv = false;
     for (int pass = 0; pass < 2; ++pass) {
       const int T = pass ? P.T2 : P.T1;
-      const bool use_lam2 = pass == 1 && P.second_pass_posterior;
+      const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
       for (int c = tid; c < m; c += nt) {
         A12[c] = make_float2(0.0f, 0.0f);
         info[c] = (InfoT)0;
       }
+      if (pass == 0 && soft)
+        for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
       __syncthreads();
       int t = 0;
       for (;;) {
@@ -237,6 +242,32 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
             conv = ok;
             it[pass] = t;
             break;
+          }
+          // intermittent soft DC (application j = t / soft_period of the first
+          // pass): the rows of D nominate on this iteration's posteriors (row h
+          // hashed as j * rows(D) + h), the nominees' priors rise by soft_shift;
+          // cutw (empty during the first pass) collects the nominees
+          if (pass == 0 && soft && !ok && t % P.soft_period == 0) {
+            const u64 rbase = (u64)(t / P.soft_period) * (u64)C.md;
+            for (int h = tid; h < C.md; h += nt) {
+              const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
+              if (deg == 0) continue;
+              int cols[32];
+              float vals[32];
+              for (int k = 0; k < deg; ++k) {
+                cols[k] = C.d_col[e0 + k];
+                vals[k] = bpdc_dev::sat(L[cols[k]], LS);
+              }
+              const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, P.tie_eps, P.tie_lowest, P.seed,
+                                                     (u64)(a.shot_offset + b), rbase + (u64)h);
+              atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+            }
+            __syncthreads();
+            for (int v = tid; v < n; v += nt)
+              if ((cutw[v >> 5] >> (v & 31)) & 1u) lam2[v] = lam2[v] + P.soft_shift;
+            __syncthreads();
+            for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
+            __syncthreads();
           }
         }
         ++t;

@@ -38,6 +38,8 @@ struct KParams {
   int tie_lowest;
   unsigned long long seed;
   int rule;  // 0 scaled min-sum, 1 product-sum
+  int soft_period;   // intermittent soft DC every soft_period first-pass iterations (0: off)
+  float soft_shift;  // prior-LLR increase of each soft nominee
 };
 
 // Output / input buffers of one single-code decode.

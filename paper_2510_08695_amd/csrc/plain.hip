@@ -27,6 +27,7 @@ struct PlainWs {
   unsigned char* st; // [B]
   unsigned char* conv;  // [B]
   short* it;         // [B][2]
+  u32* mark;         // [ceil(n/32)][B] nominees of one soft-DC application
 };
 
 __host__ __device__ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -41,6 +42,7 @@ PlainWs carve(const DevCode& c, int64_t B, void* ws) {
   w.st = (unsigned char*)p; p += align_up((size_t)B);
   w.conv = (unsigned char*)p; p += align_up((size_t)B);
   w.it = (short*)p; p += align_up(sizeof(short) * 2 * (size_t)B);
+  w.mark = (u32*)p; p += align_up(sizeof(u32) * (size_t)((c.n + 31) / 32) * B);
   return w;
 }
 
@@ -133,12 +135,13 @@ __global__ void k_check(DevCode c, PlainWs w, const uint64_t* syn, int sw64, int
 }
 
 // Variable half: L_v = prior + sum of r (ascending check order), q = sat(L - r).
-__global__ void k_var(DevCode c, PlainWs w, int64_t B, int pass, float lsat) {
+// The first pass reads its per-shot prior from lam2 when soft DC shifts it.
+__global__ void k_var(DevCode c, PlainWs w, int64_t B, int pass, float lsat, int soft) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   if (b >= B) return;
   if (w.st[b] != (pass ? ST_PASS2 : ST_PASS1)) return;
-  const float lam = pass ? w.lam2[(size_t)v * B + b] : c.lam[v];
+  const float lam = (pass || soft) ? w.lam2[(size_t)v * B + b] : c.lam[v];
   const int k0 = c.h_col_ptr[v], k1 = c.h_col_ptr[v + 1];
   if (lam == __builtin_huge_valf()) {  // cut column: prior probability 0
     for (int k = k0; k < k1; ++k) w.q[(size_t)c.h_col_edge[k] * B + b] = lsat;
@@ -167,11 +170,51 @@ __global__ void k_stop(DevCode c, PlainWs w, const uint64_t* syn, int sw64, int6
       par ^= (w.L[(size_t)c.h_col[e] * B + b] <= 0.0f) ? 1u : 0u;
     ok = (par == 0u);
   }
+  w.conv[b] = ok ? 1 : 0;
   if ((stop && ok) || t >= T) {
     w.conv[b] = ok ? 1 : 0;
     w.it[2 * b + pass] = (short)t;
     w.st[b] = pass ? ST_DONE2 : (ok ? ST_DONE1 : ST_NEED_DC);
   }
+}
+
+// First-pass prior of every shot for soft DC: the channel prior.
+__global__ void k_init_soft(DevCode c, PlainWs w, int64_t B) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (b >= B) return;
+  w.lam2[(size_t)v * B + b] = c.lam[v];
+}
+
+// Intermittent soft DC (application j of the first pass), one thread per shot
+// still in its first pass with H e != s: every row of D nominates as in DC
+// (row h hashed as j * rows(D) + h) and each nominee's prior LLR rises by
+// `shift` once, however many rows nominate it.
+__global__ void k_soft(DevCode c, PlainWs w, int64_t B, int64_t shot_offset, float lsat, float tie_eps,
+                       int tie_lowest, u64 seed, u64 j, float shift) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (w.st[b] != ST_PASS1 || w.conv[b]) return;
+  const int nw = (c.n + 31) >> 5;
+  for (int i = 0; i < nw; ++i) w.mark[(size_t)i * B + b] = 0u;
+  for (int h = 0; h < c.md; ++h) {
+    const int e0 = c.d_row_ptr[h], deg = c.d_row_ptr[h + 1] - e0;
+    if (deg == 0) continue;
+    int cols[32];
+    float vals[32];
+    for (int k = 0; k < deg; ++k) {
+      cols[k] = c.d_col[e0 + k];
+      vals[k] = bpdc_dev::sat(w.L[(size_t)cols[k] * B + b], lsat);
+    }
+    const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, tie_eps, tie_lowest, seed, (u64)(shot_offset + b),
+                                           j * (u64)c.md + (u64)h);
+    w.mark[(size_t)(pick >> 5) * B + b] |= 1u << (pick & 31);
+  }
+  for (int v = 0; v < c.n; ++v)
+    if ((w.mark[(size_t)(v >> 5) * B + b] >> (v & 31)) & 1u) {
+      const size_t i = (size_t)v * B + b;
+      w.lam2[i] = w.lam2[i] + shift;
+    }
 }
 
 // Degeneracy cutting, one thread per shot whose first pass failed.
@@ -253,7 +296,8 @@ hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream) {
 
 size_t plain_workspace_bytes(const DevCode& c, int64_t B) {
   return align_up(sizeof(float) * (size_t)c.E * B) * 2 + align_up(sizeof(float) * (size_t)c.n * B) * 2 +
-         align_up((size_t)B) * 2 + align_up(sizeof(short) * 2 * (size_t)B);
+         align_up((size_t)B) * 2 + align_up(sizeof(short) * 2 * (size_t)B) +
+         align_up(sizeof(u32) * (size_t)((c.n + 31) / 32) * B);
 }
 
 hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, void* ws,
@@ -266,6 +310,8 @@ hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, 
   const dim3 blk(256);
   const unsigned gx = (unsigned)((B + 255) / 256);
   hipLaunchKernelGGL(k_init_state, dim3(gx), blk, 0, stream, w.st, w.it, B);
+  const int soft = p.soft_period > 0;
+  if (soft) hipLaunchKernelGGL(k_init_soft, dim3(gx, c.n), blk, 0, stream, c, w, B);
   for (int pass = 0; pass < 2; ++pass) {
     const int T = pass ? p.T2 : p.T1;
     if (pass == 1)
@@ -275,8 +321,11 @@ hipError_t plain_decode(const DevCode& c, const KParams& p, const DecodeIO& io, 
     for (int t = 1; t <= T; ++t) {
       hipLaunchKernelGGL(k_check, dim3(gx, c.m), blk, 0, stream, c, w, io.syn, sw64, B, pass, p.alpha,
                          p.lsat, p.rule);
-      hipLaunchKernelGGL(k_var, dim3(gx, c.n), blk, 0, stream, c, w, B, pass, p.lsat);
+      hipLaunchKernelGGL(k_var, dim3(gx, c.n), blk, 0, stream, c, w, B, pass, p.lsat, soft);
       hipLaunchKernelGGL(k_stop, dim3(gx), blk, 0, stream, c, w, io.syn, sw64, B, pass, t, T, p.stop);
+      if (soft && pass == 0 && t % p.soft_period == 0 && t < T)
+        hipLaunchKernelGGL(k_soft, dim3(gx), blk, 0, stream, c, w, B, io.shot_offset, p.lsat, p.tie_eps,
+                           p.tie_lowest, (u64)p.seed, (u64)(t / p.soft_period), p.soft_shift);
     }
   }
   hipLaunchKernelGGL(k_output, dim3(gx), blk, 0, stream, c, w, B, p.lsat, io.corr, io.flags, io.post,

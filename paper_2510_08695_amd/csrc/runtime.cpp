@@ -395,6 +395,10 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
 
 // ---- group kernel: tile selection ---------------------------------------------------------
 
+// Whether the group kernel keeps a per-shot prior array in LDS (the
+// posterior second pass, or soft DC in the first pass).
+bool group_prior_array(const bpdc_plan_s* p) { return p->kp.second_pass_posterior != 0 || p->kp.soft_period > 0; }
+
 // Bytes of the group kernel's packed per-check word: the r-sign bit of every
 // edge of the row and the argmin position.
 int code_info_bytes(const bpdc::DevCode& d) { return d.max_row_deg <= 12 ? 2 : (d.max_row_deg <= 27 ? 4 : 8); }
@@ -404,7 +408,7 @@ bool group_fits(const bpdc_plan_s* p, const bpdc::DevCode& d, std::string* why) 
     *why = "row degree above 58";
     return false;
   }
-  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, code_info_bytes(d));
+  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), code_info_bytes(d));
   if (lds > (size_t)p->max_lds) {
     *why = "per-shot state of " + std::to_string(lds) + " bytes exceeds the LDS of one workgroup";
     return false;
@@ -478,7 +482,7 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   const bpdc::DevCode& d = p->codes[code]->dev;
   bpdc::GroupTile base;
   base.info_bytes = code_info_bytes(d);
-  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, p->kp.second_pass_posterior != 0, base.info_bytes);
+  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes);
   std::vector<int> cands;
   for (int t : {64, 128, 256, 512, 1024}) {
     const int work = std::max(d.n, d.m);
@@ -729,6 +733,11 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     return fail(BPDC_ERR_INVALID_ARG, "bad rule");
   if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_GROUP)
     return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain and lane kernel families only");
+  if (P.soft_period < 0 || P.soft_period > 32767) return fail(BPDC_ERR_INVALID_ARG, "soft_period must be in [0, 32767]");
+  if (P.soft_period > 0 && !(P.soft_shift >= 0.0f && std::isfinite(P.soft_shift)))
+    return fail(BPDC_ERR_INVALID_ARG, "soft_shift must be finite and >= 0");
+  if (P.soft_period > 0 && kernel == BPDC_KERNEL_LANE)
+    return fail(BPDC_ERR_UNSUPPORTED, "soft DC runs on the group and plain kernel families only");
   if (P.rule == BPDC_RULE_PRODUCT_SUM)
     for (int i = 0; i < ncodes; ++i)
       if (codes[i]->dev.max_row_deg > 32)
@@ -750,6 +759,8 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   p->kp.tie_lowest = P.tie_break == BPDC_TIE_LOWEST_INDEX;
   p->kp.seed = P.seed;
   p->kp.rule = P.rule;
+  p->kp.soft_period = P.soft_period;
+  p->kp.soft_shift = P.soft_period > 0 ? P.soft_shift : 0.0f;
   HIP_TRY(hipGetDevice(&p->device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
@@ -773,7 +784,9 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     }
     const int rule = p->kp.rule;
     std::string why_lane, why_group;
-    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why_lane);
+    const bool soft = p->kp.soft_period > 0;
+    const bool lane_ok = !soft && bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why_lane);
+    if (soft) why_lane = "soft DC runs on the group and plain kernel families only";
     if (rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_AUTO) {
       // product-sum: the lane kernel when the code fits one lane, else plain
       if (lane_ok) {
@@ -804,6 +817,8 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     } else if (group_ok) {
       if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_GROUP;
+    } else if (soft) {
+      cp.kernel = BPDC_KERNEL_PLAIN;  // soft DC on a code too large for one workgroup's LDS
     } else {
       return fail(BPDC_ERR_UNSUPPORTED, "no fused kernel for code %d (lane: %s; group: %s)", i, why_lane.c_str(),
                   why_group.c_str());
@@ -825,7 +840,8 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
       maxw = std::max(maxw, std::max(codes[i]->dev.n, codes[i]->dev.m));
     }
     for (int i = 0; i < ncodes; ++i)
-      lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, posterior, info_bytes));
+      lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, group_prior_array(p.get()),
+                                                   info_bytes));
     if (lds > (size_t)p->max_lds) {
       p->multi_ok = false;
       p->multi_why = "largest per-shot state exceeds the LDS of one workgroup";
@@ -1028,6 +1044,7 @@ static bpdc_status wms_check(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
   if (p->kp.second_pass_posterior)
     return fail(BPDC_ERR_UNSUPPORTED, "weighted min-sum supports the channel second-pass prior only");
   if (p->kp.rule != BPDC_RULE_MIN_SUM) return fail(BPDC_ERR_UNSUPPORTED, "weighted decoding is min-sum only");
+  if (p->kp.soft_period > 0) return fail(BPDC_ERR_UNSUPPORTED, "weighted decoding has no soft DC");
   const bpdc::DevCode& d = p->codes[code]->dev;
   if (bpdc::wms_backward_lds(d, K) > (size_t)p->max_lds || bpdc::wms_forward_lds(d) > (size_t)p->max_lds)
     return fail(BPDC_ERR_UNSUPPORTED, "code too large for the weighted min-sum kernels (LDS)");

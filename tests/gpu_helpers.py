@@ -14,7 +14,8 @@ def oracle_params(prm, second_pass: str) -> oracle.OracleParams:
                                second_pass_prior=second_pass, stop_on_converge=prm.stop_on_converge,
                                llr_sat=prm.llr_sat, tie_eps=prm.tie_eps,
                                tie_break="lowest" if prm.tie_break == 1 else "hash", seed=prm.seed,
-                               rule=getattr(prm, "rule", 0))
+                               rule=getattr(prm, "rule", 0), soft_period=getattr(prm, "soft_period", 0),
+                               soft_shift=float(np.float32(getattr(prm, "soft_shift", 0.0))))
 
 
 def gpu_decode(plan, code, syndromes: np.ndarray, code_index: int = 0, shot_offset: int = 0,

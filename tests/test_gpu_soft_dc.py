@@ -1,0 +1,82 @@
+"""Intermittent soft DC (the extension proposed in Sec. V) on the GPU against the
+float32 oracle (needs an MI355X): every K first-pass iterations, while H e != s,
+DC's nominees get their prior LLR raised by beta.  Group and plain kernel
+families; every output bit-exact with the float32 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import assert_bit_exact, gpu_decode, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2510_08695_amd as P
+    P.lib()
+    return P
+
+
+def _code(name, p):
+    return synth.toric_code(6, p=p) if name == "toric6" else synth.bb_code(name, p=p)
+
+
+CASES = [
+    # name, p, shots, T, K, beta, stop
+    ("bb144", 0.05, 1500, (100, 100), 5, 0.5, True),
+    ("bb144", 0.06, 800, (60, 40), 10, 2.0, True),
+    ("bb72", 0.06, 800, (40, 40), 3, 0.75, False),
+    ("toric6", 0.07, 1000, (50, 50), 4, 1.0, True),
+]
+
+
+@pytest.mark.parametrize("kernel", ["group", "plain"])
+@pytest.mark.parametrize("name,p,shots,T,K,beta,stop", CASES)
+def test_soft_dc_bit_exact_vs_float32_oracle(P, kernel, name, p, shots, T, K, beta, stop):
+    code = _code(name, p)
+    sh = synth.make_shots(code, shots, 9000 + shots)
+    sp = P.PRIOR_POSTERIOR if code.second_pass == "posterior" else P.PRIOR_CHANNEL
+    prm = P.Params(max_iter=T, alpha=0.625, second_pass_prior=sp, seed=41, stop_on_converge=stop,
+                   soft_period=K, soft_shift=beta)
+    kid = P.KERNEL_GROUP if kernel == "group" else P.KERNEL_PLAIN
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    print(f"case {name} p={p} K={K} beta={beta} stop={stop} kernel={kernel}", flush=True)
+    g = gpu_decode(plan, code, sh.syndromes, shot_offset=7)
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, code.second_pass), precision="f32", shot_offset=7)
+    assert ((ref["flags"] & 2) != 0).sum() > 0
+    assert_bit_exact(g, ref, code.n)
+    # soft DC changed the decoding (against BP+DC without it)
+    off = oracle.decode(code, sh.syndromes, oracle_params(P.Params(max_iter=T, alpha=0.625, second_pass_prior=sp,
+                                                                   seed=41, stop_on_converge=stop),
+                                                          code.second_pass), precision="f32", shot_offset=7,
+                        want_post=False)
+    assert (off["iters"] != ref["iters"]).any()
+
+
+def test_soft_dc_plans(P):
+    code = P.Code.from_problem(synth.bb_code("bb144", p=0.05))
+    prm = P.Params(max_iter=(50, 50), soft_period=5, soft_shift=0.5)
+    assert P.Plan([code], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_GROUP
+    with pytest.raises(P.BpdcError):
+        P.Plan([code], prm, kernel=P.KERNEL_LANE)
+    for bad in (dict(soft_period=-1), dict(soft_period=5, soft_shift=-1.0), dict(soft_period=5, soft_shift=float("inf"))):
+        with pytest.raises(P.BpdcError):
+            P.Plan([code], P.Params(max_iter=(50, 50), **bad), kernel=P.KERNEL_GROUP)
+
+
+def test_soft_dc_multi_code_launch(P):
+    """The multi-code group launch runs soft DC too (two codes, mixed shots, each shot
+    checked against the float32 oracle at its index in the mixed batch)."""
+    from test_gpu_group import _check_multi, _mixed_batch, _run_multi
+    codes = [synth.bb_code("bb72", p=0.06), synth.bb_code("bb144", p=0.05)]
+    prm = P.Params(max_iter=(60, 60), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=5,
+                   soft_period=6, soft_shift=1.0)
+    plan = P.Plan([P.Code.from_problem(c) for c in codes], prm, kernel=P.KERNEL_GROUP)
+    code_of_shot, syn, per_code = _mixed_batch(P, codes, [70, 90], 91)
+    outs, corr_off = _run_multi(P, plan, codes, code_of_shot, syn)
+    _check_multi(P, prm, codes, per_code, outs[0], corr_off)
