@@ -86,7 +86,7 @@ typedef struct {
  * the tie tolerance open; these are the knobs). */
 typedef struct {
   int32_t max_iter[2];       /* T before DC, T after DC (each >= 1) */
-  float alpha;               /* min-sum scale: r = alpha * min |q| */
+  float alpha;               /* min-sum scale: r = alpha * min |q| (finite, >= 0) */
   int32_t second_pass_prior; /* BPDC_PRIOR_* */
   int32_t stop_on_converge;  /* 1: stop a pass once H e = s (Sec. II.C); 0: run all iterations */
   float llr_sat;             /* messages and reported posteriors saturate at +-llr_sat (> 0, finite) */

@@ -36,8 +36,10 @@ struct GCode {
   const int32_t* d_row_ptr;
   const int32_t* d_col;
   const float* lam;
-  const int32_t* v_ell;  // [max_col_deg][n]: (check << 6) | position in the check's row, ascending checks; -1 pad
-  const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; -1 pad
+  const int32_t* v_ell;  // [max_col_deg][n]: (check << 6) | position in the check's row, ascending checks;
+                         // padded with check m (a dummy whose messages are -0)
+  const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; padded with column n
+                         // (a dummy whose posterior is +inf)
   int max_col_deg, max_row_deg;
 };
 
@@ -125,18 +127,30 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     const GCode C = a.codes[ci];
     const int n = C.n, m = C.m;
     const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
-    // LDS carve for this code
-    float2* A12 = (float2*)smem;                   // [m] (alpha*min1, alpha*min2) per check
-    float* L = (float*)(A12 + m);                  // [n]
-    u32* cutw = (u32*)(L + n);                     // [ceil(n/32)]
+    // LDS carve for this code; check m and column n are the dummies the
+    // padding entries of the adjacency tables point at
+    float2* A12 = (float2*)smem;                   // [m + 1] (alpha*min1, alpha*min2) per check
+    float* L = (float*)(A12 + m + 1);              // [n + 1]
+    u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     // [n] per-shot prior: the first pass's under soft DC, the second pass's
     // with the posterior prior
     float* lam2 = (float*)(synw + ((m + 31) >> 5));
     const bool soft = P.soft_period > 0;
-    // [m], aligned to its size
-    InfoT* info = (InfoT*)(((uintptr_t)(lam2 + ((P.second_pass_posterior || soft) ? n : 0)) + sizeof(InfoT) - 1) &
-                           ~(uintptr_t)(sizeof(InfoT) - 1));
+    // [m + 1], aligned to its size (offset arithmetic from smem keeps the LDS address space)
+    const size_t info_off =
+        ((size_t)((unsigned char*)(lam2 + ((P.second_pass_posterior || soft) ? n : 0)) - smem) + sizeof(InfoT) - 1) &
+        ~(size_t)(sizeof(InfoT) - 1);
+    InfoT* info = (InfoT*)(smem + info_off);
+    // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
+    // padded row entry reads L = +inf, so q saturates at lsat: it is never a
+    // new minimum, leaves the second minimum (a median with lsat) and the
+    // sign parity unchanged
+    if (tid == 0) {
+      A12[m] = make_float2(-0.0f, -0.0f);
+      info[m] = (InfoT)0;
+      L[n] = INF;
+    }
 
     const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
     for (int w = tid; w < ((m + 31) >> 5); w += nt) {
@@ -166,26 +180,22 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
           if (Lv != INF) {
             // entries in chunks of 4, all loads of a chunk issued before the sums;
-            // padding entries (-1) read check 0 and add nothing
+            // padding entries read the dummy check and add -0
+            const int pad = m << 6;
             for (int k0 = 0; k0 < C.max_col_deg; k0 += 4) {
               int ent[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : -1;
+              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : pad;
               float2 aa[4];
               W in[4];
 #pragma unroll
               for (int j = 0; j < 4; ++j) {
-                const int c = (ent[j] >= 0 ? ent[j] : 0) >> 6;
+                const int c = ent[j] >> 6;
                 aa[j] = A12[c];
                 in[j] = (W)info[c];
               }
 #pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const float r = decode_r2<InfoT>(aa[j], in[j], ent[j] & 63);
-                const float s = Lv + r;
-                Lv = (ent[j] >= 0) ? s : Lv;
-              }
-              if (ent[3] < 0) break;
+              for (int j = 0; j < 4; ++j) Lv = Lv + decode_r2<InfoT>(aa[j], in[j], ent[j] & 63);
             }
           }
           L[v] = Lv;
@@ -200,37 +210,58 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           const float2 ao = A12[c];
           const W io = (W)info[c];
           float m1 = LS, m2 = LS;
-          int amin = 0, d = 0;
+          int amin = 0;
           W sb = 0;
-          u32 par = (synw[c >> 5] >> (c & 31)) & 1u;
+          // Bit 31 of parw is the parity of the hard decisions [L <= 0]: a
+          // posterior is never -0 (it starts from a prior that is not -0 and
+          // adds messages; x + y is -0 only when both are), so L <= 0 exactly
+          // when bits(L) - 1 has its top bit set (+0 wraps to all ones, +inf
+          // and positive values stay below 2^31).  For the same reason
+          // q = sat(L - r) is never -0 and its sign bit is [q < 0].
+          u32 parw = 0u;
+          const int am_old = (int)(io >> InfoTraits<InfoT>::kPosShift);
           // columns in chunks of 8, all loads of a chunk issued before the
-          // updates; padding entries (-1) contribute nothing
+          // updates; padding entries read the dummy column (L = +inf) and
+          // change nothing
           for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
             int vv[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? gload(C.c_ell, (k0 + j) * m + c) : -1;
+            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? gload(C.c_ell, (k0 + j) * m + c) : n;
             float Lj[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Lj[j] = L[vv[j] >= 0 ? vv[j] : 0];
+            for (int j = 0; j < 8; ++j) Lj[j] = L[vv[j]];
+            // the old state rebased to this chunk: sign bits at 0..7, argmin - k0
+            const u32 ioc = (u32)(io >> k0);
+            const int amc = am_old - k0;
+            int amj = -1;  // position in the chunk of the newest minimum, if any
+            u32 sbc = 0u;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-              const bool ok = vv[j] >= 0;
-              const int k = k0 + j;
               const float Lv = Lj[j];
-              par ^= (ok && Lv <= 0.0f) ? 1u : 0u;
-              const float q = bpdc_dev::sat(Lv - decode_r2<InfoT>(ao, io, k), LS);
-              const float aq = ok ? fabsf(q) : INF;
-              amin = (aq < m1) ? k : amin;
+              parw ^= __float_as_uint(Lv) - 1u;
+              // r_old: alpha * (min2 on the old argmin, min1 elsewhere) with its
+              // sign bit; the magnitude is +0 or positive (alpha >= 0), or -0 on
+              // the dummy check, whose sign bits are 0
+              const float mag = (amc == j) ? ao.y : ao.x;
+              const float r = __uint_as_float(((ioc << (31 - j)) & 0x80000000u) | __float_as_uint(mag));
+              const float q = bpdc_dev::sat(Lv - r, LS);
+              const float aq = fabsf(q);
+              const bool lt = aq < m1;
+              amj = lt ? j : amj;
               m2 = __builtin_amdgcn_fmed3f(aq, m1, m2);
-              m1 = fminf(aq, m1);
-              sb |= (W)((ok && q < 0.0f) ? 1u : 0u) << k;
-              d = ok ? k + 1 : d;
+              m1 = lt ? aq : m1;
+              sbc |= (__float_as_uint(q) >> 31) << j;
             }
-            if (vv[7] < 0) break;
+            amin = (amj >= 0) ? k0 + amj : amin;
+            sb |= (W)sbc << k0;
           }
+          const u32 par = (parw >> 31) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
           bad |= (int)par;
           const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
-          const W rb = rp ? (sb ^ (((W)1 << d) - (W)1)) : sb;
+          // flip every sign bit on an odd parity: the bits past the row's
+          // degree are read only by padding entries, whose q saturates anyway
+          constexpr W kSignMask = ((W)1 << InfoTraits<InfoT>::kPosShift) - (W)1;
+          const W rb = rp ? (sb ^ kSignMask) : sb;
           A12[c] = make_float2(P.alpha * m1, P.alpha * m2);
           info[c] = (InfoT)(rb | ((W)amin << InfoTraits<InfoT>::kPosShift));
         }
@@ -353,8 +384,9 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }  // namespace
 
 size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes) {
-  size_t words = (size_t)n + 2 * (size_t)m + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
-  return words * 4 + (size_t)m * info_bytes + 8 + 16;  // 8: alignment of the info array
+  // L[n + 1], A12[m + 1] (two words), cut and syndrome words, per-shot prior, info[m + 1]
+  size_t words = (size_t)(n + 1) + 2 * (size_t)(m + 1) + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
+  return words * 4 + (size_t)(m + 1) * info_bytes + 8 + 16;  // 8: alignment of the info array
 }
 
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,

@@ -25,8 +25,8 @@ struct DevCode {
   int32_t* d_row_ptr = nullptr;  // [md+1]
   int32_t* d_col = nullptr;      // [dnnz]
   float* lam = nullptr;          // [n]
-  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 6 | position in row), ascending rows; -1 pad
-  int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; -1 pad
+  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 6 | position in row), ascending rows; pad m << 6
+  int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; pad n
 };
 
 // Runtime decoder parameters as the kernels see them.

@@ -646,7 +646,9 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
   }
   std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
   // padded column-major adjacency for the group kernel (one coalesced load per edge)
-  std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, -1), cell((size_t)std::max(1, d.max_row_deg) * g.m, -1);
+  // padding: check m / column n, dummies that the group kernel keeps in LDS
+  std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, g.m << 6),
+      cell((size_t)std::max(1, d.max_row_deg) * g.m, g.n);
   for (int v = 0; v < g.n; ++v)
     for (int k = cp[v]; k < cp[v + 1]; ++k) {
       const int edge = ce[k], r = er[edge];
@@ -726,7 +728,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     return fail(BPDC_ERR_INVALID_ARG, "max_iter must be in [1, 32767]");
   if (!(P.llr_sat > 0.0f) || !std::isfinite(P.llr_sat)) return fail(BPDC_ERR_INVALID_ARG, "llr_sat must be finite and > 0");
   if (!(P.tie_eps >= 0.0f) || !std::isfinite(P.tie_eps)) return fail(BPDC_ERR_INVALID_ARG, "tie_eps must be >= 0");
-  if (!std::isfinite(P.alpha)) return fail(BPDC_ERR_INVALID_ARG, "alpha must be finite");
+  if (!std::isfinite(P.alpha) || !(P.alpha >= 0.0f)) return fail(BPDC_ERR_INVALID_ARG, "alpha must be finite and >= 0");
   if (P.second_pass_prior != BPDC_PRIOR_CHANNEL && P.second_pass_prior != BPDC_PRIOR_POSTERIOR)
     return fail(BPDC_ERR_INVALID_ARG, "bad second_pass_prior");
   if (P.rule != BPDC_RULE_MIN_SUM && P.rule != BPDC_RULE_PRODUCT_SUM)
@@ -751,7 +753,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   p->params = P;
   p->kp.T1 = P.max_iter[0];
   p->kp.T2 = P.max_iter[1];
-  p->kp.alpha = P.alpha;
+  p->kp.alpha = P.alpha + 0.0f;  // -0 becomes +0: every message magnitude is then +0 or positive
   p->kp.lsat = P.llr_sat;
   p->kp.tie_eps = P.tie_eps;
   p->kp.second_pass_posterior = P.second_pass_prior == BPDC_PRIOR_POSTERIOR;
