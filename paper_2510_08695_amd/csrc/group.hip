@@ -66,36 +66,49 @@ struct GArgs {
   KParams p;
 };
 
-// Packed per-check info: low bits r-sign of each edge, top bits argmin
-// position; 16 bits for rows of at most 12 edges, 32 for at most 27, 64 for
-// at most 58 (Word: the register type the kernel computes it in).
-template <class InfoT>
-struct InfoTraits;
+// Per-check state, one 16-byte record (one LDS access): alpha*min1,
+// alpha*min2, the r-sign bit of every edge of the row and the argmin position.
+// Narrow rows (at most 32 edges): 32 sign bits and the argmin in its own word;
+// wide rows (at most 58): 64 sign bits whose top six hold the argmin.
+template <bool Wide>
+struct CheckRec;
 template <>
-struct InfoTraits<uint16_t> {
-  static constexpr int kPosShift = 12;
+struct __align__(16) CheckRec<false> {
+  float a1, a2;
+  u32 sgn, amin;
   using Word = u32;
+  static constexpr Word kSignMask = 0xffffffffu;
+  __device__ __forceinline__ int argmin() const { return (int)amin; }
+  __device__ __forceinline__ Word signs() const { return sgn; }
+  __device__ __forceinline__ u32 sign_bit(int k) const { return (sgn >> k) & 1u; }
+  __device__ __forceinline__ void set(float x1, float x2, Word s, int am) {
+    a1 = x1; a2 = x2; sgn = s; amin = (u32)am;
+  }
 };
 template <>
-struct InfoTraits<u32> {
-  static constexpr int kPosShift = 27;
-  using Word = u32;
-};
-template <>
-struct InfoTraits<u64> {
-  static constexpr int kPosShift = 58;
+struct __align__(16) CheckRec<true> {
+  float a1, a2;
+  u32 lo, hi;
   using Word = u64;
+  static constexpr Word kSignMask = ((u64)1 << 58) - 1u;
+  __device__ __forceinline__ int argmin() const { return (int)(hi >> 26); }
+  __device__ __forceinline__ Word signs() const { return ((u64)hi << 32) | lo; }
+  __device__ __forceinline__ u32 sign_bit(int k) const { return ((k < 32 ? lo : hi) >> (k & 31)) & 1u; }
+  __device__ __forceinline__ void set(float x1, float x2, Word s, int am) {
+    a1 = x1; a2 = x2; lo = (u32)s; hi = (u32)(s >> 32) | ((u32)am << 26);
+  }
 };
 
 __device__ __forceinline__ int popc_word(u32 x) { return __builtin_popcount(x); }
 __device__ __forceinline__ int popc_word(u64 x) { return __builtin_popcountll(x); }
 
-// r of the edge at row position k from the packed check state: alpha*min2 on
-// the argmin edge, alpha*min1 elsewhere, sign bit k of the info word.
-template <class InfoT>
-__device__ __forceinline__ float decode_r2(float2 a12, typename InfoTraits<InfoT>::Word info, int k) {
-  const float mag = ((int)(info >> InfoTraits<InfoT>::kPosShift) == k) ? a12.y : a12.x;
-  return __uint_as_float(__float_as_uint(mag) ^ ((u32)((info >> k) & 1u) << 31));
+// r of the edge at row position k: alpha*min2 on the argmin edge, alpha*min1
+// elsewhere, with sign bit k.  The magnitude is +0 or positive (alpha >= 0),
+// or -0 on the dummy check, whose sign bits are 0, so the sign is or-ed in.
+template <bool Wide>
+__device__ __forceinline__ float rec_r(const CheckRec<Wide>& s, int k) {
+  const float mag = (s.argmin() == k) ? s.a2 : s.a1;
+  return __uint_as_float(__float_as_uint(mag) | (s.sign_bit(k) << 31));
 }
 
 // Load through a global-address-space pointer (the code tables are reached
@@ -104,7 +117,7 @@ __device__ __forceinline__ int gload(const int32_t* p, int i) {
   return ((const __attribute__((address_space(1))) int32_t*)p)[i];
 }
 
-template <class InfoT>
+template <bool Wide>
 __global__ void __launch_bounds__(1024) k_group(GArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long sIdx;
@@ -114,7 +127,8 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
   const KParams& P = a.p;
   const float LS = P.lsat;
   const float INF = __builtin_huge_valf();
-  using W = typename InfoTraits<InfoT>::Word;
+  using Rec = CheckRec<Wide>;
+  using W = typename Rec::Word;
 
   for (;;) {
     if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
@@ -129,26 +143,20 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
     const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
     // LDS carve for this code; check m and column n are the dummies the
     // padding entries of the adjacency tables point at
-    float2* A12 = (float2*)smem;                   // [m + 1] (alpha*min1, alpha*min2) per check
-    float* L = (float*)(A12 + m + 1);              // [n + 1]
+    Rec* S = (Rec*)smem;                           // [m + 1] check states
+    float* L = (float*)(S + m + 1);                // [n + 1]
     u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     // [n] per-shot prior: the first pass's under soft DC, the second pass's
     // with the posterior prior
     float* lam2 = (float*)(synw + ((m + 31) >> 5));
     const bool soft = P.soft_period > 0;
-    // [m + 1], aligned to its size (offset arithmetic from smem keeps the LDS address space)
-    const size_t info_off =
-        ((size_t)((unsigned char*)(lam2 + ((P.second_pass_posterior || soft) ? n : 0)) - smem) + sizeof(InfoT) - 1) &
-        ~(size_t)(sizeof(InfoT) - 1);
-    InfoT* info = (InfoT*)(smem + info_off);
     // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
     // padded row entry reads L = +inf, so q saturates at lsat: it is never a
     // new minimum, leaves the second minimum (a median with lsat) and the
     // sign parity unchanged
     if (tid == 0) {
-      A12[m] = make_float2(-0.0f, -0.0f);
-      info[m] = (InfoT)0;
+      S[m].set(-0.0f, -0.0f, 0, 0);
       L[n] = INF;
     }
 
@@ -165,8 +173,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
       const int T = pass ? P.T2 : P.T1;
       const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
       for (int c = tid; c < m; c += nt) {
-        A12[c] = make_float2(0.0f, 0.0f);
-        info[c] = (InfoT)0;
+        S[c].set(0.0f, 0.0f, 0, 0);
       }
       if (pass == 0 && soft)
         for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
@@ -186,16 +193,11 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
               int ent[4];
 #pragma unroll
               for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : pad;
-              float2 aa[4];
-              W in[4];
+              Rec sr[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const int c = ent[j] >> 6;
-                aa[j] = A12[c];
-                in[j] = (W)info[c];
-              }
+              for (int j = 0; j < 4; ++j) sr[j] = S[ent[j] >> 6];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) Lv = Lv + decode_r2<InfoT>(aa[j], in[j], ent[j] & 63);
+              for (int j = 0; j < 4; ++j) Lv = Lv + rec_r<Wide>(sr[j], ent[j] & 63);
             }
           }
           L[v] = Lv;
@@ -207,8 +209,8 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
         // when the pass ends here ----
         int bad = 0;
         for (int c = tid; c < m; c += nt) {
-          const float2 ao = A12[c];
-          const W io = (W)info[c];
+          const Rec so = S[c];
+          const W io = so.signs();
           float m1 = LS, m2 = LS;
           int amin = 0;
           W sb = 0;
@@ -219,7 +221,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           // and positive values stay below 2^31).  For the same reason
           // q = sat(L - r) is never -0 and its sign bit is [q < 0].
           u32 parw = 0u;
-          const int am_old = (int)(io >> InfoTraits<InfoT>::kPosShift);
+          const int am_old = so.argmin();
           // columns in chunks of 8, all loads of a chunk issued before the
           // updates; padding entries read the dummy column (L = +inf) and
           // change nothing
@@ -242,7 +244,7 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
               // r_old: alpha * (min2 on the old argmin, min1 elsewhere) with its
               // sign bit; the magnitude is +0 or positive (alpha >= 0), or -0 on
               // the dummy check, whose sign bits are 0
-              const float mag = (amc == j) ? ao.y : ao.x;
+              const float mag = (amc == j) ? so.a2 : so.a1;
               const float r = __uint_as_float(((ioc << (31 - j)) & 0x80000000u) | __float_as_uint(mag));
               const float q = bpdc_dev::sat(Lv - r, LS);
               const float aq = fabsf(q);
@@ -260,10 +262,8 @@ __global__ void __launch_bounds__(1024) k_group(GArgs a) {
           const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
           // flip every sign bit on an odd parity: the bits past the row's
           // degree are read only by padding entries, whose q saturates anyway
-          constexpr W kSignMask = ((W)1 << InfoTraits<InfoT>::kPosShift) - (W)1;
-          const W rb = rp ? (sb ^ kSignMask) : sb;
-          A12[c] = make_float2(P.alpha * m1, P.alpha * m2);
-          info[c] = (InfoT)(rb | ((W)amin << InfoTraits<InfoT>::kPosShift));
+          const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
+          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin);
         }
         if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
         __syncthreads();
@@ -384,9 +384,11 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 }  // namespace
 
 size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes) {
-  // L[n + 1], A12[m + 1] (two words), cut and syndrome words, per-shot prior, info[m + 1]
-  size_t words = (size_t)(n + 1) + 2 * (size_t)(m + 1) + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
-  return words * 4 + (size_t)(m + 1) * info_bytes + 8 + 16;  // 8: alignment of the info array
+  // check records [m + 1] (16 bytes each, either width), L[n + 1], cut and
+  // syndrome words, per-shot prior
+  (void)info_bytes;
+  size_t words = (size_t)(n + 1) + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
+  return (size_t)(m + 1) * 16 + words * 4 + 16;
 }
 
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
@@ -413,9 +415,8 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
   (void)hipGetLastError();  // report only this launch's errors
   hipError_t e = fill_u64((uint64_t*)queue, 0, 1, stream);
   if (e != hipSuccess) return e;
-  if (info_bytes == 2) hipLaunchKernelGGL(k_group<uint16_t>, dim3(grid), dim3(threads), lds, stream, a);
-  else if (info_bytes == 4) hipLaunchKernelGGL(k_group<u32>, dim3(grid), dim3(threads), lds, stream, a);
-  else hipLaunchKernelGGL(k_group<u64>, dim3(grid), dim3(threads), lds, stream, a);
+  if (info_bytes == 8) hipLaunchKernelGGL(k_group<true>, dim3(grid), dim3(threads), lds, stream, a);
+  else hipLaunchKernelGGL(k_group<false>, dim3(grid), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -423,24 +424,21 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
 // process and device), then report how many workgroups of `threads` threads
 // and `lds` bytes fit on a compute unit.
 int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds) {
-  // raise the dynamic-LDS limit of the three instantiations once; a refusal leaves
+  // raise the dynamic-LDS limit of both instantiations once; a refusal leaves
   // the default limit (and its error is cleared so that it is not reported
   // by a later launch check)
   static int raised_to = -1;
   if (raised_to != max_lds) {
-    if (hipFuncSetAttribute((const void*)k_group<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+    if (hipFuncSetAttribute((const void*)k_group<false>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
             hipSuccess ||
-        hipFuncSetAttribute((const void*)k_group<u32>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void*)k_group<u64>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+        hipFuncSetAttribute((const void*)k_group<true>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
             hipSuccess)
       (void)hipGetLastError();
     raised_to = max_lds;
   }
   int nb = 0;
-  hipError_t e = info_bytes == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<uint16_t>, threads, lds)
-                 : info_bytes == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u32>, threads, lds)
-                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<u64>, threads, lds);
+  hipError_t e = info_bytes == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<true>, threads, lds)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<false>, threads, lds);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;

@@ -66,7 +66,7 @@ struct GroupTile {
   int threads = 256;
   int grid = 0;          // persistent workgroups
   size_t lds_bytes = 0;  // dynamic LDS per workgroup
-  int info_bytes = 4;    // per-check info word: 2 (row degree <= 12), 4 (<= 27) or 8 bytes (<= 58)
+  int info_bytes = 4;    // sign bits per check record: 4 bytes (row degree <= 32) or 8 (<= 58)
 };
 
 // Group decoder (group.hip): persistent fused kernel, one workgroup per shot,

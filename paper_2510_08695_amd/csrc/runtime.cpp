@@ -399,9 +399,9 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
 // posterior second pass, or soft DC in the first pass).
 bool group_prior_array(const bpdc_plan_s* p) { return p->kp.second_pass_posterior != 0 || p->kp.soft_period > 0; }
 
-// Bytes of the group kernel's packed per-check word: the r-sign bit of every
-// edge of the row and the argmin position.
-int code_info_bytes(const bpdc::DevCode& d) { return d.max_row_deg <= 12 ? 2 : (d.max_row_deg <= 27 ? 4 : 8); }
+// Sign-bit width of the group kernel's per-check record: 4 bytes for rows of
+// at most 32 edges, 8 for longer rows.
+int code_info_bytes(const bpdc::DevCode& d) { return d.max_row_deg <= 32 ? 4 : 8; }
 
 bool group_fits(const bpdc_plan_s* p, const bpdc::DevCode& d, std::string* why) {
   if (d.max_row_deg > 58) {
@@ -829,7 +829,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   // multi-code launch: the group kernel over all codes, LDS sized for the largest
   p->multi_ok = true;
   {
-    int info_bytes = 2;
+    int info_bytes = 4;
     size_t lds = 0;
     int maxw = 0;
     for (int i = 0; i < ncodes; ++i) {
