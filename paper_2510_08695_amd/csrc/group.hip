@@ -117,6 +117,32 @@ __device__ __forceinline__ int gload(const int32_t* p, int i) {
   return ((const __attribute__((address_space(1))) int32_t*)p)[i];
 }
 
+// DC nomination of one row of D (the rule of bpdc_device.h's dc_pick, in the
+// same float operations) streamed from the row's column list and the
+// posteriors in LDS, with no per-thread arrays: the row maximum of the
+// saturated posteriors, the tie threshold, the number of ties, then the
+// chosen tie in ascending column order.
+__device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg, const float* L, float lsat,
+                                           float tie_eps, int tie_lowest, u64 seed, u64 shot, u64 row) {
+  float lmax = bpdc_dev::sat(L[gload(dcol, e0)], lsat);
+  for (int k = 1; k < deg; ++k) lmax = fmaxf(lmax, bpdc_dev::sat(L[gload(dcol, e0 + k)], lsat));
+  const float scale = fmaxf(1.0f, fabsf(lmax));
+  const float thr = lmax - tie_eps * scale;
+  int nt = 0;
+  for (int k = 0; k < deg; ++k) nt += (bpdc_dev::sat(L[gload(dcol, e0 + k)], lsat) >= thr) ? 1 : 0;
+  int want = 0;
+  if (!tie_lowest && nt > 1) want = (int)bpdc_dev::scale_draw(bpdc_dev::tie_hash(seed, shot, row), (u32)nt);
+  int seen = 0;
+  for (int k = 0; k < deg; ++k) {
+    const int col = gload(dcol, e0 + k);
+    if (bpdc_dev::sat(L[col], lsat) >= thr) {
+      if (seen == want) return col;
+      ++seen;
+    }
+  }
+  return gload(dcol, e0);
+}
+
 // At most 64 VGPRs (eight waves per SIMD): two workgroups of 1024 threads then
 // share a compute unit, so one's barriers overlap the other's work (measured
 // 1.3-1.5x over the 128-register build, whose single workgroup per CU stalls
@@ -287,14 +313,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             for (int h = tid; h < C.md; h += nt) {
               const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
               if (deg == 0) continue;
-              int cols[32];
-              float vals[32];
-              for (int k = 0; k < deg; ++k) {
-                cols[k] = C.d_col[e0 + k];
-                vals[k] = bpdc_dev::sat(L[cols[k]], LS);
-              }
-              const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, P.tie_eps, P.tie_lowest, P.seed,
-                                                     (u64)(a.shot_offset + b), rbase + (u64)h);
+              const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+                                           (u64)(a.shot_offset + b), rbase + (u64)h);
               atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
             }
             __syncthreads();
@@ -312,14 +332,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       for (int h = tid; h < C.md; h += nt) {
         const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
         if (deg == 0) continue;
-        int cols[32];
-        float vals[32];
-        for (int k = 0; k < deg; ++k) {
-          cols[k] = C.d_col[e0 + k];
-          vals[k] = bpdc_dev::sat(L[cols[k]], LS);
-        }
-        const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, P.tie_eps, P.tie_lowest, P.seed,
-                                               (u64)(a.shot_offset + b), (u64)h);
+        const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+                                     (u64)(a.shot_offset + b), (u64)h);
         atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
       }
       __syncthreads();
