@@ -38,6 +38,7 @@ COUNTERS = {
     "hgp64": (GROUP_SOURCES, "profiles/k_group_hgp64_counters.md"),
     "surface7": (LANE_SOURCES, "profiles/bpdc_lane_kernel_surface7_ps_p001_1e6.md"),
     "circuit": (GROUP_SOURCES, "profiles/k_group_circuit_bb144_T12_p0001_2e4.md"),
+    "soft": (LANE_SOURCES, "profiles/bpdc_lane_kernel_soft_bb144_p005_1e6.md"),
 }
 
 
@@ -340,6 +341,10 @@ def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None
     ler, ci = _ler(code, shots.errors, out["corr"].cpu().numpy().view(np.uint64), flags)
     n_dc = int(((flags & 2) != 0).sum())
     ops = OPS_PER_EDGE_ITER * code.H.nnz * int(iters.sum()) + OPS_PER_DC_ENTRY * code.D.nnz * n_dc
+    if getattr(prm, "soft_period", 0) > 0:
+        # soft-DC nominations: at t = K, 2K, ... below the first pass's last iteration
+        apps = int(np.clip((iters[:, 0] - 1) // prm.soft_period, 0, None).sum())
+        ops += OPS_PER_DC_ENTRY * code.D.nnz * apps
     res = {"metric": metric, "value": B / (ms / 1e3), "unit": "shots/s", "n_gpus": 1, "steps": args.steps,
            "ms_per_step": ms, "dtype": "f32", "data": "synthetic", "config": {"workload": workload,
            "shots_per_step": B, "plan": plan.info(0)},
@@ -422,8 +427,8 @@ def run_soft(args):
     """Intermittent soft DC (the extension Sec. V proposes) on the headline problem:
     BB[[144,12,12]], p = 0.05, 1e6 shots, min-sum alpha = 0.625, T = 100 + 100, channel
     second-pass prior; every 5 first-pass iterations the DC nominees' prior LLRs rise by
-    0.5.  Group kernel (the lane kernel has no soft DC); the same shots decoded without
-    soft DC by the headline lane kernel give the logical error rate it is compared with."""
+    0.5.  Lane kernel (its soft-DC variant); the group kernel with soft DC and the
+    headline lane kernel without it decode the same shots for comparison."""
     import torch
     import paper_2510_08695_amd as P
     import synth
@@ -434,23 +439,22 @@ def run_soft(args):
     seed = 2005
     res = _single(args, code, B, seed, prm, f"BB[[144,12,12]] code capacity p=0.05, {B} shots, min-sum alpha=0.625, "
                   "T=100+100, soft DC every 5 iterations with prior-LLR shift 0.5", "shots/s BP+soft DC, BB144 p=0.05",
-                  P.KERNEL_GROUP, traffic_key=None)
+                  P.KERNEL_LANE, traffic_key="soft" if B == 1_000_000 else None)
     shots = synth.make_shots(code, B, seed)
     syn = torch.from_numpy(synth.pack_bits(shots.syndromes).view(np.int64)).cuda()
     stream = torch.cuda.current_stream()
     base = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1)
-    for name, kid in (("lane", P.KERNEL_LANE), ("group", P.KERNEL_GROUP)):
-        plan = P.Plan([P.Code.from_problem(code)], base, kernel=kid)
+    for name, kid, pr in (("soft_group", P.KERNEL_GROUP, prm), ("without_soft_lane", P.KERNEL_LANE, base)):
+        plan = P.Plan([P.Code.from_problem(code)], pr, kernel=kid)
         out = plan.decode(syn, want_iters=True)
         ms = _timed(lambda: plan.decode(syn, out=out), max(1, args.steps // 2), stream)
         flags = out["flags"].cpu().numpy()
         ler, ci = _ler(code, shots.errors, out["corr"].cpu().numpy().view(np.uint64), flags)
-        res[f"without_soft_{name}"] = {"shots_per_s": B / (ms / 1e3), "ler": ler, "ler_ci95": ci,
-                                       "dc_rate": float(((flags & 2) != 0).mean()),
-                                       "mean_iters": float(out["iters"].cpu().numpy().astype(np.int64).sum()) / B}
+        res[name] = {"shots_per_s": B / (ms / 1e3), "ler": ler, "ler_ci95": ci,
+                     "dc_rate": float(((flags & 2) != 0).mean()),
+                     "mean_iters": float(out["iters"].cpu().numpy().astype(np.int64).sum()) / B}
         del plan
     print(json.dumps(res), flush=True)
-
 
 def run_phen(args):
     import paper_2510_08695_amd as P

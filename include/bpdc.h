@@ -102,9 +102,9 @@ typedef struct {
    * (>= 0, finite), i.e. its prior error odds p / (1 - p) shrink by the factor
    * e^-soft_shift; messages carry on.  The DC after a failed first pass and
    * the second pass are unchanged (the channel second-pass prior is the
-   * unshifted one).  Group and plain kernel families only (the lane family
-   * and weighted decoding return BPDC_ERR_UNSUPPORTED); AUTO picks the group
-   * family, or plain when a shot does not fit one workgroup. */
+   * unshifted one).  All three kernel families with min-sum (the lane family
+   * as its own code-specialised variant), the plain family with product-sum;
+   * weighted decoding returns BPDC_ERR_UNSUPPORTED. */
   int32_t soft_period;
   float soft_shift;
 } bpdc_params;
@@ -222,9 +222,10 @@ bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
  * 1 for plans with BPDC_PRIOR_POSTERIOR; uniform_prior = 1 for codes whose
  * priors are all equal (the kernel then takes the prior as one value); rule
  * is the plan's BPDC_RULE_* (product-sum: one lane per shot, at most 96
- * edges).  BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
+ * edges); soft = 1 for plans with soft DC (soft_period > 0; min-sum only).
+ * BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
 bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior,
-                                 int32_t uniform_prior, int32_t rule);
+                                 int32_t uniform_prior, int32_t rule, int32_t soft);
 
 const char* bpdc_status_string(bpdc_status status);
 const char* bpdc_last_error(void);

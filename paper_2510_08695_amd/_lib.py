@@ -77,7 +77,7 @@ def lib():
             "bpdc_wms_ckpt_size": [P, I32, I64, I32, C.POINTER(C.c_size_t)],
             "bpdc_wms_forward": [P, I32, P, P, I64, I64, I32, P, P, P, P, C.c_size_t, P],
             "bpdc_wms_backward": [P, I32, P, P, I64, I32, P, P, P, P, C.c_size_t, P, P],
-            "bpdc_lane_precompile": [C.POINTER(_Csr), C.POINTER(_Csr), I32, I32, I32],
+            "bpdc_lane_precompile": [C.POINTER(_Csr), C.POINTER(_Csr), I32, I32, I32, I32],
             "bpdc_plan_set_dc_stats": [P, P, I64],
         }
         for name, args in sig.items():
@@ -142,12 +142,13 @@ class Params:
         return p
 
 
-def lane_precompile(H, D, posterior: bool = False, uniform_prior: bool = True, rule: int = RULE_MIN_SUM) -> None:
+def lane_precompile(H, D, posterior: bool = False, uniform_prior: bool = True, rule: int = RULE_MIN_SUM,
+                    soft: bool = False) -> None:
     """Compile the code-specialised lane kernel into the on-disk cache (no GPU needed)."""
     h, keep_h = _csr(H)
     d, keep_d = _csr(D)
     _check(lib().bpdc_lane_precompile(C.byref(h), C.byref(d), 1 if posterior else 0,
-                                      1 if uniform_prior else 0, int(rule)))
+                                      1 if uniform_prior else 0, int(rule), 1 if soft else 0))
 
 
 class Code:

@@ -62,6 +62,8 @@ struct LaneArgs {
   float a2_init1;                 // alpha * lsat: its second minimum for a check of degree 1
   int skip0;                      // start first passes from that state (equal priors, 0 < lambda < lsat)
   unsigned long long* dcstats;    // DC diagnostics (NB_NSTAT words, accumulated) or null
+  int soft_period;                // intermittent soft DC every soft_period first-pass iterations (NB_SOFT)
+  float soft_shift;               // prior-LLR increase of each soft nominee (NB_SOFT)
 };
 
 // Posteriors in LDS as [column][shot slot of the wave], one slot per lane
@@ -223,7 +225,11 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 #else
 #define NB_LAM1(i) lamrow[i]
 #endif
-#if NB_POSTERIOR
+#if NB_SOFT
+// soft DC: every pass reads the shot's own prior (shifted by soft DC in the
+// first pass; the second pass's channel or posterior prior after DC)
+#define NB_LAM(i, v) myLam2[(v) * NB_LSTR]
+#elif NB_POSTERIOR
 #define NB_LAM(i, v) (pass ? myLam2[(v) * NB_LSTR] : NB_LAM1(i))
 #else
 #define NB_LAM(i, v) NB_LAM1(i)
@@ -237,8 +243,8 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
   using namespace bpdc_lane;
   __shared__ float sL[NB_N * NB_LSTR];
-#if NB_POSTERIOR
-  __shared__ float sLam2[NB_N * NB_LSTR];
+#if NB_POSTERIOR || NB_SOFT
+  __shared__ float sLam2[NB_N * NB_LSTR];  // per-shot prior: posterior second pass, or soft DC
 #endif
   __shared__ short sDcolP[NB_MD * NB_DMAXROW];  // D rows, padded to the largest degree
 #if !NB_DUNIFORM
@@ -277,7 +283,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
 #pragma unroll
   for (int m = 0; m < 16; ++m) asm("v_mov_b32 %0, %1" : "=v"(rolemask[m]) : "v"(0u - ((m >> role) & 1u)));
   float* myL = sL + sid + loff * NB_LSTR;
-#if NB_POSTERIOR
+#if NB_POSTERIOR || NB_SOFT
   float* myLam2 = sLam2 + sid + loff * NB_LSTR;
 #endif
   const float LS = a.lsat;
@@ -411,6 +417,19 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       it1 = fresh ? 0 : it1;
     }
     if (__ballot(shot >= 0) == 0) break;
+#if NB_SOFT
+    // new shots start their first pass from the channel prior
+    {
+      u64 fm = __ballot(fresh) & leaders;
+      while (fm) {
+        const int src = __ffsll((long long)fm) - 1;
+        const int ssid = src / NB_G;
+        fm &= fm - 1;
+        for (int u = lane; u < NB_N; u += 64) sLam2[u * NB_LSTR + ssid] = a.lam[u];
+      }
+      __syncthreads();
+    }
+#endif
 
     // ---- one sweep: variable half of iteration t, check half of iteration t+1 -----
 #if !NB_UNIFORM_PRIOR
@@ -494,6 +513,9 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
           const float x = sL[u * NB_LSTR + ssid];
           sLam2[u * NB_LSTR + ssid] = cv ? __builtin_huge_valf() : bpdc_dev::sat(x, LS);
         }
+#elif NB_SOFT
+        // channel second pass: the unshifted prior (cut columns are +inf through C)
+        for (int u = lane; u < NB_N; u += 64) sLam2[u * NB_LSTR + ssid] = a.lam[u];
 #endif
         if (first == src) {
 #pragma unroll
@@ -561,6 +583,64 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
       shot = finish ? -1 : shot;
       want = want || finish;
     }
+#if NB_SOFT
+    // ---- intermittent soft DC: at t = K, 2K, ... of a first pass with H e != s
+    // the rows of D nominate on this iteration's posteriors (the j-th
+    // application hashes row h as j * rows(D) + h) and the nominees' priors
+    // rise by soft_shift; the next sweep reads them ---------------------------------
+    {
+      const bool softnow = (shot >= 0) && !done && pass == 0 && !conv && t >= 1 && (t % a.soft_period) == 0;
+      u64 sm = __ballot(softnow) & leaders;
+      while (sm) {
+        const int src = __ffsll((long long)sm) - 1;
+        const int ssid = src / NB_G;
+        sm &= sm - 1;
+        const long long sshot = readlane64(shot, src);
+        const int st = __builtin_amdgcn_readlane(t, src);
+        const u64 rbase = (u64)(st / a.soft_period) * (u64)NB_MD;
+        for (int w = lane; w < NB_G * NB_RC32; w += 64) sCut[w / NB_RC32][w % NB_RC32] = 0u;
+        constexpr int kRowIt = (NB_MD + 63) / 64;
+        int pick[kRowIt];
+#pragma unroll
+        for (int it = 0; it < kRowIt; ++it) {
+          const int h = lane + 64 * it;
+          pick[it] = -1;
+          if (h < NB_MD) {
+            int cols[NB_DMAXROW];
+            float vals[NB_DMAXROW];
+#pragma unroll
+            for (int k = 0; k < NB_DMAXROW; ++k) {
+              cols[k] = sDcolP[h * NB_DMAXROW + k];
+              vals[k] = bpdc_dev::sat(sL[cols[k] * NB_LSTR + ssid], LS);
+            }
+#if NB_DUNIFORM
+            const int deg = NB_DMAXROW;
+#else
+            const int deg = sDdeg[h];
+#endif
+            if (deg > 0)
+              pick[it] = bpdc_dev::dc_pick<NB_DMAXROW>(cols, vals, deg, a.tie_eps, a.tie_lowest, a.seed,
+                                                       (u64)(a.shot_offset + sshot), rbase + (u64)h);
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kRowIt; ++it) {
+          if (pick[it] >= 0) {
+            const int pr = sColRow[pick[it]];
+            atomicOr(&sCut[pr & 3][(pr >> 2) >> 5], 1u << ((pr >> 2) & 31));
+          }
+        }
+        __syncthreads();
+        for (int u = lane; u < NB_N; u += 64) {
+          const int cr = sColRow[u];
+          const int r = cr >> 2, hb = cr & 3;
+          if ((sCut[hb][r >> 5] >> (r & 31)) & 1u) sLam2[u * NB_LSTR + ssid] = sLam2[u * NB_LSTR + ssid] + a.soft_shift;
+        }
+        __syncthreads();
+      }
+    }
+#endif
     t += 1;
   }
   if (a.dcstats) {

@@ -154,11 +154,12 @@ void find_group(const HostGraph& g, int max_lanes, LaneGroup* out) {
   out->block = {blocks[0]};
 }
 
-bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, std::string* why) {
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, bool soft, std::string* why) {
   auto fail = [&](const char* msg) {
     if (why) *why = msg;
     return false;
   };
+  if (rule && soft) return fail("soft DC with product-sum runs on the plain kernel only");
   if (rule) {
     // product-sum: one lane per shot and one register per edge
     max_lanes = 1;
@@ -177,14 +178,14 @@ bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, 
   if (g.n / G > 128) return fail("more than 128 columns per lane");
   if (g.m / G > 80) return fail("more than 80 checks per lane");
   const size_t lstr = 64 / G + 1;
-  const size_t lds = (size_t)g.n * lstr * 4 * (posterior ? 2 : 1) + g.drows.size() * max_deg(g.drows) * 2 +
+  const size_t lds = (size_t)g.n * lstr * 4 * ((posterior || soft) ? 2 : 1) + g.drows.size() * max_deg(g.drows) * 2 +
                      g.drows.size() + (size_t)G * ((g.n / G + 31) / 32) * 4 + (size_t)g.n * 2 +
                      (size_t)G * (g.n / G) * 4 + 32 * (size_t)G * ((g.m / G + 31) / 32) * 4;
   if (lds > 64 * 1024) return fail("per-wave LDS above 64 KiB");
   return true;
 }
 
-LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule) {
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule, bool soft) {
   const int n = g.n, m = g.m, md = (int)g.drows.size();
   if (rule) max_lanes = 1;  // product-sum: one lane per shot
   LaneGroup grp;
@@ -270,7 +271,7 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     << nwc << "\n#define NB_DNNZ " << std::max<size_t>(dnnz, 1) << "\n#define NB_DMAXROW "
     << std::max(1, max_deg(g.drows)) << "\n#define NB_DUNIFORM " << (uniform_drows ? 1 : 0)
     << "\n#define NB_POSTERIOR " << (posterior ? 1 : 0) << "\n#define NB_G " << G << "\n#define NB_PS "
-    << (rule ? 1 : 0);
+    << (rule ? 1 : 0) << "\n#define NB_SOFT " << (soft ? 1 : 0);
   for (int k = 1; k < 4; ++k) o << "\n#define NB_LOFF" << k << " " << (k < G ? grp.off[k] : 0);
   o << "\n#define NB_UNIFORM_PRIOR " << (uniform_prior ? 1 : 0) << "\n";
   // column -> (row << 2 | lane in group), for the cooperative DC code

@@ -40,8 +40,9 @@ struct LaneSpec {
 };
 
 void find_group(const HostGraph& g, int max_lanes, LaneGroup* out);
-// rule: 0 scaled min-sum, 1 product-sum (one lane per shot, one register per edge)
-bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, std::string* why);
-LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule);
+// rule: 0 scaled min-sum, 1 product-sum (one lane per shot, one register per edge);
+// soft: intermittent soft DC in the first pass (min-sum only; a per-shot prior array in LDS)
+bool lane_eligible(const HostGraph& g, bool posterior, int max_lanes, int rule, bool soft, std::string* why);
+LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int max_lanes, int rule, bool soft);
 
 }  // namespace bpdc

@@ -301,6 +301,8 @@ struct LaneArgsHost {
   float a2_init1;
   int skip0;
   unsigned long long* dcstats;
+  int soft_period;
+  float soft_shift;
 };
 
 // Largest lane group the lane kernel may use for one shot (1, 2 or 4).
@@ -316,12 +318,12 @@ bool uniform_prior(const bpdc_code_s* c) {
   return true;
 }
 
-bpdc_status build_lane(bpdc_code c, bool posterior, int rule, int num_cu, LaneKernel* lk) {
+bpdc_status build_lane(bpdc_code c, bool posterior, int rule, bool soft, int num_cu, LaneKernel* lk) {
   std::string why;
-  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why))
+  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes(), rule);
+  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes(), rule, soft);
   std::string src = spec.src;
   bpdc_status st = lane_code_object(src, &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
@@ -371,6 +373,8 @@ bpdc_status lane_launch(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, c
   a.d_col = c->dev.d_col;
   a.queue = queue;
   a.dcstats = (unsigned long long*)io.dcstats;
+  a.soft_period = p->kp.soft_period;
+  a.soft_shift = p->kp.soft_shift;
   a.alpha = p->kp.alpha;
   a.lsat = p->kp.lsat;
   a.tie_eps = p->kp.tie_eps;
@@ -691,7 +695,7 @@ bpdc_status bpdc_code_info(bpdc_code c, int32_t* n, int32_t* m, int32_t* md, int
 }
 
 bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior, int32_t uniform_prior,
-                                 int32_t rule) {
+                                 int32_t rule, int32_t soft) {
   if (rule != BPDC_RULE_MIN_SUM && rule != BPDC_RULE_PRODUCT_SUM) return fail(BPDC_ERR_INVALID_ARG, "bad rule");
   std::string why;
   if (!H || !D || !csr_ok(H, &why) || !csr_ok(D, &why) || H->cols != D->cols)
@@ -709,11 +713,11 @@ bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t p
   g.drows.resize(D->rows);
   for (int r = 0; r < D->rows; ++r)
     for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
-  if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), rule, &why))
+  if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), rule, soft != 0, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  return lane_code_object(bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes(), rule).src,
-                          &image, nullptr);
+  return lane_code_object(
+      bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes(), rule, soft != 0).src, &image, nullptr);
 }
 
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
@@ -738,8 +742,6 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   if (P.soft_period < 0 || P.soft_period > 32767) return fail(BPDC_ERR_INVALID_ARG, "soft_period must be in [0, 32767]");
   if (P.soft_period > 0 && !(P.soft_shift >= 0.0f && std::isfinite(P.soft_shift)))
     return fail(BPDC_ERR_INVALID_ARG, "soft_shift must be finite and >= 0");
-  if (P.soft_period > 0 && kernel == BPDC_KERNEL_LANE)
-    return fail(BPDC_ERR_UNSUPPORTED, "soft DC runs on the group and plain kernel families only");
   if (P.rule == BPDC_RULE_PRODUCT_SUM)
     for (int i = 0; i < ncodes; ++i)
       if (codes[i]->dev.max_row_deg > 32)
@@ -787,12 +789,11 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     const int rule = p->kp.rule;
     std::string why_lane, why_group;
     const bool soft = p->kp.soft_period > 0;
-    const bool lane_ok = !soft && bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, &why_lane);
-    if (soft) why_lane = "soft DC runs on the group and plain kernel families only";
+    const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why_lane);
     if (rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_AUTO) {
       // product-sum: the lane kernel when the code fits one lane, else plain
       if (lane_ok) {
-        if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+        if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
         cp.kernel = BPDC_KERNEL_LANE;
       } else {
         cp.kernel = BPDC_KERNEL_PLAIN;
@@ -801,7 +802,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     }
     const bool group_ok = group_fits(p.get(), c->dev, &why_group);
     if (kernel == BPDC_KERNEL_LANE) {
-      if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
       continue;
     }
@@ -814,7 +815,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     // AUTO: the code-specialised lane kernel when the code fits one lane,
     // otherwise the autotuned group kernel
     if (lane_ok) {
-      if ((st = build_lane(c, posterior, rule, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
     } else if (group_ok) {
       if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;

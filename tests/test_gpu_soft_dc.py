@@ -1,6 +1,6 @@
 """Intermittent soft DC (the extension proposed in Sec. V) on the GPU against the
 float32 oracle (needs an MI355X): every K first-pass iterations, while H e != s,
-DC's nominees get their prior LLR raised by beta.  Group and plain kernel
+DC's nominees get their prior LLR raised by beta.  Lane, group and plain kernel
 families; every output bit-exact with the float32 oracle."""
 import numpy as np
 import pytest
@@ -35,7 +35,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("kernel", ["group", "plain"])
+@pytest.mark.parametrize("kernel", ["lane", "group", "plain"])
 @pytest.mark.parametrize("name,p,shots,T,K,beta,stop", CASES)
 def test_soft_dc_bit_exact_vs_float32_oracle(P, kernel, name, p, shots, T, K, beta, stop):
     code = _code(name, p)
@@ -43,7 +43,7 @@ def test_soft_dc_bit_exact_vs_float32_oracle(P, kernel, name, p, shots, T, K, be
     sp = P.PRIOR_POSTERIOR if code.second_pass == "posterior" else P.PRIOR_CHANNEL
     prm = P.Params(max_iter=T, alpha=0.625, second_pass_prior=sp, seed=41, stop_on_converge=stop,
                    soft_period=K, soft_shift=beta)
-    kid = P.KERNEL_GROUP if kernel == "group" else P.KERNEL_PLAIN
+    kid = {"lane": P.KERNEL_LANE, "group": P.KERNEL_GROUP, "plain": P.KERNEL_PLAIN}[kernel]
     plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
     print(f"case {name} p={p} K={K} beta={beta} stop={stop} kernel={kernel}", flush=True)
     g = gpu_decode(plan, code, sh.syndromes, shot_offset=7)
@@ -61,9 +61,14 @@ def test_soft_dc_bit_exact_vs_float32_oracle(P, kernel, name, p, shots, T, K, be
 def test_soft_dc_plans(P):
     code = P.Code.from_problem(synth.bb_code("bb144", p=0.05))
     prm = P.Params(max_iter=(50, 50), soft_period=5, soft_shift=0.5)
-    assert P.Plan([code], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_GROUP
+    assert P.Plan([code], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_LANE
+    # product-sum with soft DC: plain only
+    surf = P.Code.from_problem(synth.rotated_surface_code(5, p=0.03))
+    ps = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM,
+                  soft_period=5, soft_shift=0.5)
+    assert P.Plan([surf], ps, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
     with pytest.raises(P.BpdcError):
-        P.Plan([code], prm, kernel=P.KERNEL_LANE)
+        P.Plan([surf], ps, kernel=P.KERNEL_LANE)
     for bad in (dict(soft_period=-1), dict(soft_period=5, soft_shift=-1.0), dict(soft_period=5, soft_shift=float("inf"))):
         with pytest.raises(P.BpdcError):
             P.Plan([code], P.Params(max_iter=(50, 50), **bad), kernel=P.KERNEL_GROUP)
@@ -80,3 +85,32 @@ def test_soft_dc_multi_code_launch(P):
     code_of_shot, syn, per_code = _mixed_batch(P, codes, [70, 90], 91)
     outs, corr_off = _run_multi(P, plan, codes, code_of_shot, syn)
     _check_multi(P, prm, codes, per_code, outs[0], corr_off)
+
+
+def test_soft_dc_lane_full_size_sampled(P):
+    """The benchmark configuration (BB144, p = 0.05, 1e6 shots, K = 5, beta = 0.5) on
+    the lane kernel in one launch: sampled blocks bit-exact with the float32 oracle,
+    and every output equal to the group kernel's on the same shots."""
+    import torch
+    code = synth.bb_code("bb144", p=0.05)
+    B = 1_000_000
+    sh = synth.make_shots(code, B, 2005)
+    prm = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1,
+                   soft_period=5, soft_shift=0.5)
+    syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
+    outs = {}
+    for kid in (P.KERNEL_LANE, P.KERNEL_GROUP):
+        plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+        o = plan.decode(syn, want_cut=True, want_iters=True)
+        torch.cuda.synchronize()
+        outs[kid] = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
+    for k in outs[P.KERNEL_LANE]:
+        np.testing.assert_array_equal(outs[P.KERNEL_LANE][k], outs[P.KERNEL_GROUP][k], err_msg=k)
+    corr = synth.unpack_bits(outs[P.KERNEL_LANE]["corr"].view(np.uint64), code.n)
+    for lo in (0, 500_000, 999_000):
+        hi = lo + 1000
+        ref = oracle.decode(code, sh.syndromes[lo:hi], oracle_params(prm, "channel"), precision="f32",
+                            shot_offset=lo, want_post=False)
+        np.testing.assert_array_equal(corr[lo:hi], ref["ehat"])
+        np.testing.assert_array_equal(outs[P.KERNEL_LANE]["flags"][lo:hi], ref["flags"])
+        np.testing.assert_array_equal(outs[P.KERNEL_LANE]["iters"][lo:hi], ref["iters"])
