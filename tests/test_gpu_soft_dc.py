@@ -114,3 +114,38 @@ def test_soft_dc_lane_full_size_sampled(P):
         np.testing.assert_array_equal(corr[lo:hi], ref["ehat"])
         np.testing.assert_array_equal(outs[P.KERNEL_LANE]["flags"][lo:hi], ref["flags"])
         np.testing.assert_array_equal(outs[P.KERNEL_LANE]["iters"][lo:hi], ref["iters"])
+
+
+def test_soft_dc_lane_zero_shift_equals_bpdc(P):
+    """beta = 0: the lane kernel's soft-DC variant reproduces the headline lane
+    kernel's outputs bit for bit (the nominations run but shift nothing)."""
+    code = synth.bb_code("bb144", p=0.05)
+    sh = synth.make_shots(code, 3000, 9400)
+    base = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=3)
+    zero = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=3,
+                    soft_period=4, soft_shift=0.0)
+    c = P.Code.from_problem(code)
+    a = gpu_decode(P.Plan([c], base, kernel=P.KERNEL_LANE), code, sh.syndromes)
+    b = gpu_decode(P.Plan([c], zero, kernel=P.KERNEL_LANE), code, sh.syndromes)
+    for k in ("flags", "iters", "ehat", "cut"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
+
+
+def test_soft_dc_lane_dc_stats_equal_plain(P):
+    """DC diagnostics of a soft-DC decode: the lane kernel's soft variant and the
+    plain kernel count the same DC shots, cut sizes and spread bins."""
+    import torch
+    code = synth.bb_code("bb144", p=0.06)
+    sh = synth.make_shots(code, 4000, 9500)
+    prm = P.Params(max_iter=(60, 60), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=8,
+                   soft_period=5, soft_shift=0.5)
+    stats = []
+    for kid in (P.KERNEL_LANE, P.KERNEL_PLAIN):
+        plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+        st = torch.zeros(103 + code.n, dtype=torch.int64, device="cuda")
+        plan.set_dc_stats(st)
+        gpu_decode(plan, code, sh.syndromes, want_post=False)
+        stats.append(st.cpu().numpy())
+    assert stats[0][101] > 0
+    np.testing.assert_array_equal(stats[0], stats[1])

@@ -98,3 +98,13 @@ def test_lane_kernel_generation_and_compilation(P, tmp_path, monkeypatch):
     big = synth.hgp_code(synth.random_regular_classical(16, 4001), with_logicals=False)
     with pytest.raises(P.BpdcError, match="unsupported"):
         P.lane_precompile(big.H, big.D)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; --gpus 2 exits with a message (before any GPU call)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
