@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-diag", action="store_true", help="skip the untimed DC-diagnostics pass")
     ap.add_argument("--workload", default="bb144",
-                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit", "soft"],
+                    choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit", "soft", "toric6ps"],
                     help="bb144: the headline configuration (default); the others are the "
                          "secondary configurations, each printing its own JSON line")
     ap.add_argument("--dem-form", default="open", choices=["open", "paper"])
@@ -115,7 +115,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "bb144":
         {"toric6": run_toric6, "phen": run_phen, "hgp64": run_hgp64, "wms": run_wms,
-         "surface7": run_surface7, "circuit": run_circuit, "soft": run_soft}[args.workload](args)
+         "surface7": run_surface7, "circuit": run_circuit, "soft": run_soft,
+         "toric6ps": run_toric6ps}[args.workload](args)
         return
     p, B = args.p, args.shots
     code = synth.bb_code("bb144", p=p)
@@ -454,6 +455,20 @@ def run_soft(args):
                      "dc_rate": float(((flags & 2) != 0).mean()),
                      "mean_iters": float(out["iters"].cpu().numpy().astype(np.int64).sum()) / B}
         del plan
+    print(json.dumps(res), flush=True)
+
+def run_toric6ps(args):
+    """Toric L = 6 with product-sum BP (the paper's rule for surface-type codes),
+    T = n = 72 per pass, posterior second pass, code capacity p = 0.05, 1e6 shots:
+    144 edges, beyond the lane kernel's product-sum mode, so the group kernel."""
+    import paper_2510_08695_amd as P
+    import synth
+    code = synth.toric_code(6, p=0.05)
+    prm = P.Params(max_iter=(72, 72), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=3,
+                   rule=P.RULE_PRODUCT_SUM)
+    B = args.shots
+    res = _single(args, code, B, 11, prm, f"toric L=6 code capacity p=0.05, {B} shots, product-sum, T=72+72, "
+                  "posterior second pass", "shots/s BP+DC product-sum toric L=6 p=0.05", P.KERNEL_GROUP)
     print(json.dumps(res), flush=True)
 
 def run_phen(args):

@@ -61,9 +61,10 @@ enum { BPDC_TIE_HASH = 0, BPDC_TIE_LOWEST_INDEX = 1 };
  * r = alpha * min over the other |q|, or product-sum,
  * r = alpha * 2 atanh(prod over the other tanh(|q| / 2)) (alpha = 1 for the
  * plain rule), each saturated at llr_sat and signed by the syndrome bit and
- * the other signs.  Product-sum runs on the plain kernel family and, for codes
- * of at most 96 edges, on the lane family (one lane per shot); not on the
- * group family, the multi-code launch or weighted decoding. */
+ * the other signs.  Product-sum runs on the plain kernel family, on the lane
+ * family for codes of at most 96 edges (one lane per shot) and on the group
+ * family for rows of at most 8 edges; not in the multi-code launch or
+ * weighted decoding. */
 enum { BPDC_RULE_MIN_SUM = 0, BPDC_RULE_PRODUCT_SUM = 1 };
 
 /* Kernel family of a plan. */
@@ -118,7 +119,8 @@ typedef struct bpdc_plan_s* bpdc_plan; /* launch configuration for one or more c
  * once to float.  Copies everything to the current device; synchronous.
  * Row degree of H is limited to 64, column degree of H to 16, row degree of D
  * to 32 (BPDC_ERR_UNSUPPORTED otherwise); the group kernel family runs rows
- * of up to 58 edges, product-sum rows of up to 32. */
+ * of up to 58 edges (product-sum: 8), the plain family product-sum rows of
+ * up to 32. */
 bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double* h_priors,
                              bpdc_code* out);
 bpdc_status bpdc_code_destroy(bpdc_code code);

@@ -147,7 +147,11 @@ __device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg,
 // share a compute unit, so one's barriers overlap the other's work (measured
 // 1.3-1.5x over the 128-register build, whose single workgroup per CU stalls
 // the unit at every barrier; the few spills are outside the inner loops).
-template <bool Wide>
+// PS: the product-sum rule (Sec. II.C), rows of at most 8 edges: per-edge r
+// in LDS instead of check records, the leave-one-out products of tanh(|q|/2)
+// left to right in row order and the column sums in ascending check order,
+// with bpdc_device.h's float32 tanh / atanh, as in the plain and lane kernels.
+template <bool Wide, bool PS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_group(GArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long sIdx;
@@ -172,9 +176,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int n = C.n, m = C.m;
     const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
     // LDS carve for this code; check m and column n are the dummies the
-    // padding entries of the adjacency tables point at
-    Rec* S = (Rec*)smem;                           // [m + 1] check states
-    float* L = (float*)(S + m + 1);                // [n + 1]
+    // padding entries of the adjacency tables point at.  Product-sum keeps
+    // the r of every edge (CSR order) where min-sum keeps check records.
+    const int E = PS ? C.h_row_ptr[m] : 0;
+    Rec* S = (Rec*)smem;                           // [m + 1] check states (min-sum)
+    float* R = (float*)smem;                       // [E] per-edge r (product-sum)
+    float* L = PS ? (float*)(smem + (((size_t)E * 4 + 15) & ~(size_t)15)) : (float*)(S + m + 1);  // [n + 1]
     u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     // [n] per-shot prior: the first pass's under soft DC, the second pass's
@@ -186,7 +193,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // new minimum, leaves the second minimum (a median with lsat) and the
     // sign parity unchanged
     if (tid == 0) {
-      S[m].set(-0.0f, -0.0f, 0, 0);
+      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0);
       L[n] = INF;
     }
 
@@ -202,9 +209,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     for (int pass = 0; pass < 2; ++pass) {
       const int T = pass ? P.T2 : P.T1;
       const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
-      for (int c = tid; c < m; c += nt) {
-        S[c].set(0.0f, 0.0f, 0, 0);
-      }
+      if (PS)
+        for (int e = tid; e < E; e += nt) R[e] = 0.0f;
+      else
+        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0);
       if (pass == 0 && soft)
         for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
       __syncthreads();
@@ -215,7 +223,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           float Lv;
           if (use_lam2) Lv = lam2[v];
           else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
-          if (Lv != INF) {
+          if (PS && Lv != INF) {
+            for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
+          } else if (Lv != INF) {
             // entries in chunks of 4, all loads of a chunk issued before the sums;
             // padding entries read the dummy check and add -0
             const int pad = m << 6;
@@ -238,6 +248,41 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         // test H e = s (e = [L <= 0]) on the way; the new state is not used
         // when the pass ends here ----
         int bad = 0;
+        if constexpr (PS) {
+          for (int c = tid; c < m; c += nt) {
+            const int e0 = gload(C.h_row_ptr, c), deg = gload(C.h_row_ptr, c + 1) - e0;
+            const u32 sbit = (synw[c >> 5] >> (c & 31)) & 1u;
+            u32 par = sbit, neg = sbit, qn = 0u;
+            float th[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              th[j] = 1.0f;
+              if (j < deg) {
+                const float Lv = L[gload(C.h_col, e0 + j)];
+                par ^= (Lv <= 0.0f) ? 1u : 0u;
+                const float q = bpdc_dev::sat(Lv - R[e0 + j], LS);
+                const u32 qneg = (q < 0.0f) ? 1u : 0u;
+                neg ^= qneg;
+                qn |= qneg << j;
+                th[j] = bpdc_dev::tanh_half(fabsf(q));
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (j < deg) {
+                float prod = 1.0f;
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                  if (o != j && o < deg) prod = prod * th[o];
+                float mag = bpdc_dev::atanh2(prod);
+                if (!(mag < LS)) mag = LS;
+                const float val = P.alpha * mag;
+                R[e0 + j] = (neg ^ ((qn >> j) & 1u)) ? -val : val;
+              }
+            }
+            bad |= (int)par;
+          }
+        } else
         for (int c = tid; c < m; c += nt) {
           const Rec so = S[c];
           const W io = so.signs();
@@ -401,12 +446,13 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 
 }  // namespace
 
-size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes) {
-  // check records [m + 1] (16 bytes each, either width), L[n + 1], cut and
-  // syndrome words, per-shot prior
-  (void)info_bytes;
+size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edges) {
+  // check records [m + 1] (16 bytes each, either width) or, for product-sum
+  // (info_bytes 0), the per-edge r [edges]; L[n + 1], cut and syndrome words,
+  // per-shot prior
   size_t words = (size_t)(n + 1) + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
-  return (size_t)(m + 1) * 16 + words * 4 + 16;
+  const size_t head = info_bytes == 0 ? (((size_t)edges * 4 + 15) & ~(size_t)15) : (size_t)(m + 1) * 16;
+  return head + words * 4 + 16;
 }
 
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
@@ -433,8 +479,9 @@ hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const 
   (void)hipGetLastError();  // report only this launch's errors
   hipError_t e = fill_u64((uint64_t*)queue, 0, 1, stream);
   if (e != hipSuccess) return e;
-  if (info_bytes == 8) hipLaunchKernelGGL(k_group<true>, dim3(grid), dim3(threads), lds, stream, a);
-  else hipLaunchKernelGGL(k_group<false>, dim3(grid), dim3(threads), lds, stream, a);
+  if (info_bytes == 8) hipLaunchKernelGGL((k_group<true, false>), dim3(grid), dim3(threads), lds, stream, a);
+  else if (info_bytes == 0) hipLaunchKernelGGL((k_group<false, true>), dim3(grid), dim3(threads), lds, stream, a);
+  else hipLaunchKernelGGL((k_group<false, false>), dim3(grid), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 
@@ -447,16 +494,20 @@ int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds) {
   // by a later launch check)
   static int raised_to = -1;
   if (raised_to != max_lds) {
-    if (hipFuncSetAttribute((const void*)k_group<false>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
-            hipSuccess ||
-        hipFuncSetAttribute((const void*)k_group<true>, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
-            hipSuccess)
+    if (hipFuncSetAttribute((const void*)k_group<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_group<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_lds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_group<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            max_lds) != hipSuccess)
       (void)hipGetLastError();
     raised_to = max_lds;
   }
   int nb = 0;
-  hipError_t e = info_bytes == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<true>, threads, lds)
-                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<false>, threads, lds);
+  hipError_t e =
+      info_bytes == 8   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<true, false>, threads, lds)
+      : info_bytes == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<false, true>, threads, lds)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_group<false, false>, threads, lds);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;

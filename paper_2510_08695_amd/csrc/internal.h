@@ -66,12 +66,13 @@ struct GroupTile {
   int threads = 256;
   int grid = 0;          // persistent workgroups
   size_t lds_bytes = 0;  // dynamic LDS per workgroup
-  int info_bytes = 4;    // sign bits per check record: 4 bytes (row degree <= 32) or 8 (<= 58)
+  int info_bytes = 4;    // min-sum check records with 4 (row degree <= 32) or 8 (<= 58) bytes of sign
+                         // bits; 0: product-sum (per-edge r, rows of at most 8 edges)
 };
 
 // Group decoder (group.hip): persistent fused kernel, one workgroup per shot,
 // the shot's state in dynamic LDS; also the multi-code launch.
-size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes);
+size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edges);
 int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds);
 hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
                         const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,

@@ -407,12 +407,22 @@ bool group_prior_array(const bpdc_plan_s* p) { return p->kp.second_pass_posterio
 // at most 32 edges, 8 for longer rows.
 int code_info_bytes(const bpdc::DevCode& d) { return d.max_row_deg <= 32 ? 4 : 8; }
 
+// The group kernel variant of a code under a plan: 4 or 8 (min-sum check
+// records), 0 (product-sum, per-edge messages).
+int group_variant(const bpdc_plan_s* p, const bpdc::DevCode& d) {
+  return p->kp.rule == BPDC_RULE_PRODUCT_SUM ? 0 : code_info_bytes(d);
+}
+
 bool group_fits(const bpdc_plan_s* p, const bpdc::DevCode& d, std::string* why) {
   if (d.max_row_deg > 58) {
     *why = "row degree above 58";
     return false;
   }
-  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), code_info_bytes(d));
+  if (p->kp.rule == BPDC_RULE_PRODUCT_SUM && d.max_row_deg > 8) {
+    *why = "product-sum rows above 8 edges";
+    return false;
+  }
+  const size_t lds = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), group_variant(p, d), d.E);
   if (lds > (size_t)p->max_lds) {
     *why = "per-shot state of " + std::to_string(lds) + " bytes exceeds the LDS of one workgroup";
     return false;
@@ -485,8 +495,8 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
                               float* best_ms_out) {
   const bpdc::DevCode& d = p->codes[code]->dev;
   bpdc::GroupTile base;
-  base.info_bytes = code_info_bytes(d);
-  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes);
+  base.info_bytes = group_variant(p, d);
+  base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes, d.E);
   std::vector<int> cands;
   for (int t : {64, 128, 256, 512, 1024}) {
     const int work = std::max(d.n, d.m);
@@ -737,8 +747,6 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     return fail(BPDC_ERR_INVALID_ARG, "bad second_pass_prior");
   if (P.rule != BPDC_RULE_MIN_SUM && P.rule != BPDC_RULE_PRODUCT_SUM)
     return fail(BPDC_ERR_INVALID_ARG, "bad rule");
-  if (P.rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_GROUP)
-    return fail(BPDC_ERR_UNSUPPORTED, "product-sum runs on the plain and lane kernel families only");
   if (P.soft_period < 0 || P.soft_period > 32767) return fail(BPDC_ERR_INVALID_ARG, "soft_period must be in [0, 32767]");
   if (P.soft_period > 0 && !(P.soft_shift >= 0.0f && std::isfinite(P.soft_shift)))
     return fail(BPDC_ERR_INVALID_ARG, "soft_shift must be finite and >= 0");
@@ -790,17 +798,21 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     std::string why_lane, why_group;
     const bool soft = p->kp.soft_period > 0;
     const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why_lane);
+    const bool group_ok = group_fits(p.get(), c->dev, &why_group);
     if (rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_AUTO) {
-      // product-sum: the lane kernel when the code fits one lane, else plain
+      // product-sum: the lane kernel when the code fits one lane, else the
+      // group kernel when its rows and state fit, else plain
       if (lane_ok) {
         if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
         cp.kernel = BPDC_KERNEL_LANE;
+      } else if (group_ok) {
+        if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
+        cp.kernel = BPDC_KERNEL_GROUP;
       } else {
         cp.kernel = BPDC_KERNEL_PLAIN;
       }
       continue;
     }
-    const bool group_ok = group_fits(p.get(), c->dev, &why_group);
     if (kernel == BPDC_KERNEL_LANE) {
       if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
@@ -844,7 +856,7 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     }
     for (int i = 0; i < ncodes; ++i)
       lds = std::max(lds, bpdc::group_lds_bytes_nm(codes[i]->dev.n, codes[i]->dev.m, group_prior_array(p.get()),
-                                                   info_bytes));
+                                                   info_bytes, codes[i]->dev.E));
     if (lds > (size_t)p->max_lds) {
       p->multi_ok = false;
       p->multi_why = "largest per-shot state exceeds the LDS of one workgroup";

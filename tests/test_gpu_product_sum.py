@@ -58,15 +58,16 @@ def _two_prop_ok(a, b, n):
 
 
 def _kernels(P, name):
-    # the lane family runs product-sum for codes of at most 96 edges (the surface codes here)
-    return [P.KERNEL_PLAIN] + ([P.KERNEL_LANE] if name.startswith("surface") else [])
+    # the lane family runs product-sum for codes of at most 96 edges (the surface codes here);
+    # the group family for rows of at most 8 edges (all of them)
+    return [P.KERNEL_PLAIN, P.KERNEL_GROUP] + ([P.KERNEL_LANE] if name.startswith("surface") else [])
 
 
-@pytest.mark.parametrize("kname", ["plain", "lane"])
+@pytest.mark.parametrize("kname", ["plain", "lane", "group"])
 @pytest.mark.parametrize("name,p,shots,T", CASES)
 def test_product_sum_vs_float64_oracle(P, kname, name, p, shots, T):
     code = _code(name, p)
-    kid = P.KERNEL_PLAIN if kname == "plain" else P.KERNEL_LANE
+    kid = {"plain": P.KERNEL_PLAIN, "lane": P.KERNEL_LANE, "group": P.KERNEL_GROUP}[kname]
     if kid not in _kernels(P, name):
         pytest.skip("the lane family runs product-sum for codes of at most 96 edges")
     sh = synth.make_shots(code, shots, 5000 + shots)
@@ -100,30 +101,41 @@ def test_product_sum_vs_float64_oracle(P, kname, name, p, shots, T):
     np.testing.assert_array_equal(g["ehat"].astype(bool), g["post"] <= 0)
 
 
-@pytest.mark.parametrize("name,p,shots,T", [c for c in CASES if c[0].startswith("surface")])
-def test_lane_product_sum_equals_plain_bit_for_bit(P, name, p, shots, T):
-    """The two GPU product-sum decoders evaluate tanh and atanh with the same device
-    math library, in the same order (leave-one-out products left to right in column
-    order, column sums in ascending check order): every output is identical."""
+@pytest.mark.parametrize("name,p,shots,T", CASES)
+def test_product_sum_kernels_equal_bit_for_bit(P, name, p, shots, T):
+    """The GPU product-sum decoders evaluate tanh and atanh with the same float32
+    functions, in the same order (leave-one-out products left to right in column
+    order, column sums in ascending check order): every output of the lane (surface
+    codes) and group kernels equals the plain kernel's."""
     code = _code(name, p)
     sh = synth.make_shots(code, shots, 6000 + shots)
     prm = P.Params(max_iter=(T, T), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=29,
                    rule=P.RULE_PRODUCT_SUM)
     c = P.Code.from_problem(code)
     a = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_PLAIN), code, sh.syndromes)
-    b = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_LANE), code, sh.syndromes)
-    for k in ("flags", "iters", "ehat", "cut"):
-        np.testing.assert_array_equal(a[k], b[k])
-    np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
+    for kid in _kernels(P, name)[1:]:
+        b = gpu_decode(P.Plan([c], prm, kernel=kid), code, sh.syndromes)
+        for k in ("flags", "iters", "ehat", "cut"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"kernel {kid} {k}")
+        np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
 
 
 def test_product_sum_plans(P):
     prm = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM)
     small = P.Code.from_problem(synth.rotated_surface_code(5, p=0.03))
     assert P.Plan([small], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_LANE
-    big = P.Code.from_problem(synth.toric_code(6, p=0.05))  # 144 edges
-    assert P.Plan([big], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
+    big = P.Code.from_problem(synth.toric_code(6, p=0.05))  # 144 edges: group kernel
+    assert P.Plan([big], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_GROUP
     with pytest.raises(P.BpdcError):
         P.Plan([big], prm, kernel=P.KERNEL_LANE)
+    # rows of 9 to 32 edges: the plain kernel (AUTO), not the group kernel
+    wide = P.Code.from_problem(synth.hgp_code(synth.random_regular_classical(12, 5, dv=3, dc=6),
+                                              with_logicals=False, p=0.03))
+    psc = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_CHANNEL, rule=P.RULE_PRODUCT_SUM)
+    assert P.Plan([wide], psc, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
     with pytest.raises(P.BpdcError):
-        P.Plan([small], prm, kernel=P.KERNEL_GROUP)
+        P.Plan([wide], psc, kernel=P.KERNEL_GROUP)
+    # rows above 32 edges (a circuit-level DEM has 35): no product-sum kernel
+    circ = P.Code.from_problem(synth.bb_circuit_dem("bb72", 2, 0.002))
+    with pytest.raises(P.BpdcError):
+        P.Plan([circ], psc, kernel=P.KERNEL_PLAIN)
