@@ -172,3 +172,44 @@ def test_full_size_batch_sampled(P):
     dc = (flags & 2) != 0
     assert (iters[dc, 0] == 100).all() and (iters[~dc, 1] == 0).all()
     assert not (corr & cut).any()
+
+
+@pytest.mark.parametrize("variant", ["soft_lane", "soft_group", "ps_group", "circuit_group"])
+def test_edge_cases_other_kernel_modes(P, variant):
+    """Empty batches, all-zero syndromes, single shots and ragged sub-batches (with the
+    matching shot offsets) on the soft-DC lane variant, soft DC and product-sum on the
+    group kernel, and the group kernel's 64-bit check records."""
+    import torch
+    if variant == "ps_group":
+        code = synth.toric_code(6, p=0.05)
+        prm = P.Params(max_iter=(30, 30), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=2,
+                       rule=P.RULE_PRODUCT_SUM)
+    elif variant == "circuit_group":
+        code = synth.bb_circuit_dem("bb72", 2, 0.004)
+        prm = P.Params(max_iter=(60, 20), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=2)
+    else:
+        code = _code("bb144", 0.06)
+        prm = P.Params(max_iter=(40, 20), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=2,
+                       soft_period=3, soft_shift=1.0)
+    kid = P.KERNEL_LANE if variant == "soft_lane" else P.KERNEL_GROUP
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    nw_s, nw_c = (code.m + 63) // 64, (code.n + 63) // 64
+    out = plan.decode(torch.zeros((0, nw_s), dtype=torch.int64, device="cuda"))
+    assert out["corr"].shape == (0, nw_c)
+    z = np.zeros((70, code.m), np.uint8)
+    g = gpu_decode(plan, code, z)
+    assert (g["flags"] == 1).all() and (g["iters"][:, 0] == 1).all() and not g["ehat"].any()
+    sh = synth.make_shots(code, 200, 9)
+    off = 10 ** 12
+    full = gpu_decode(plan, code, sh.syndromes, shot_offset=off)
+    for lo, hi in [(0, 1), (1, 64), (64, 200)]:
+        part = gpu_decode(plan, code, sh.syndromes[lo:hi], shot_offset=off + lo)
+        for k in ("ehat", "flags", "iters", "cut"):
+            np.testing.assert_array_equal(part[k], full[k][lo:hi])
+    ps = variant == "ps_group"
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "posterior" if ps else "channel"),
+                        precision="f64" if ps else "f32", shot_offset=off)
+    if not ps:
+        assert_bit_exact(full, ref, code.n)
+    else:  # product-sum: the float64 oracle's decisions on shots with clear margins
+        np.testing.assert_array_equal(full["ehat"][ref["margin"] >= 1e-3], ref["ehat"][ref["margin"] >= 1e-3])
