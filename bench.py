@@ -634,6 +634,32 @@ def run_wms(args):
             fails += int(fl_.sum())
         return fails / B, list(wilson(fails, B))
 
+    # kernel throughput on a fixed batch: the checkpointed forward and the adjoint
+    Bk = 65536
+    shk = synth.make_shots(code, Bk, 4242)
+    synk = torch.from_numpy(synth.pack_bits(shk.syndromes).view(np.int64)).cuda()
+    w0 = torch.full((2 * E,), 0.625, dtype=torch.float32, device="cuda")
+    fwd = plan.wms_forward(w0, synk)
+    torch.cuda.synchronize()
+    n_dc_k = int(((fwd["flags"].cpu().numpy() & 2) != 0).sum())
+    ms_f = _timed(lambda: plan.wms_forward(w0, synk), 5, stream)
+    gp = torch.randn_like(fwd["post"])
+    ms_b = _timed(lambda: plan.wms_backward(w0, synk, fwd, gp), 5, stream)
+    # 8 lane-ops per edge-iteration (25 on every shot, 25 more on shots that ran DC) plus 2 per
+    # D nonzero on those shots; the adjoint is priced with the same count
+    ops_k = OPS_PER_EDGE_ITER * E * 25 * (Bk + n_dc_k) + OPS_PER_DC_ENTRY * code.D.nnz * n_dc_k
+    kern = {"batch": Bk, "dc_shots": n_dc_k,
+            "forward": {"ms": ms_f, "shots_per_s": Bk / (ms_f / 1e3),
+                        "frac": ops_k / (ms_f / 1e3) / PEAK_LANE_OPS},
+            "adjoint": {"ms": ms_b, "shots_per_s": Bk / (ms_b / 1e3),
+                        "frac": ops_k / (ms_b / 1e3) / PEAK_LANE_OPS}}
+    dom_ms = max(ms_f, ms_b)
+    roof = {"bound": "alu", "achieved": ops_k / (dom_ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s", "frac": ops_k / (dom_ms / 1e3) / PEAK_LANE_OPS, "traffic": None,
+            "traffic_unit": "bytes per launch", "launch_ms": dom_ms, "ops_per_launch": ops_k,
+            "kernel": "adjoint" if ms_b >= ms_f else "forward"}
+    del fwd, gp
+
     ler_init, ci_init = evaluate(torch.full((2 * E,), 0.625, device="cuda"))
     res = {"metric": "weighted min-sum BP+DC on BB[[144,12,12]] p=0.05: LER with trained weights at 25+25 "
                      "iterations (parity loss)",
@@ -641,7 +667,7 @@ def run_wms(args):
            "config": {"workload": "BB144 code capacity p=0.05, 2 x 432 edge scales from 0.625, batch 4096, "
                                   "25+25 unrolled iterations, checkpoint every 5, Adam lr 1e-3; evaluation on "
                                   "1e6 shots (seed 5999)", "train_steps": args.train_steps},
-           "ler_untrained": ler_init, "ler_untrained_ci95": ci_init}
+           "ler_untrained": ler_init, "ler_untrained_ci95": ci_init, "kernels": kern, "roofline": roof}
     for kind in ("parity", "bce"):
         w, secs, step_ms, losses = train(kind)
         ler, ci = evaluate(w)

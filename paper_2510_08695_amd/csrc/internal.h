@@ -104,10 +104,10 @@ size_t wms_forward_lds(const DevCode& d);
 size_t wms_backward_lds(const DevCode& d, int K);
 hipError_t wms_forward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B,
                        int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, float* ckpt,
-                       int grid, int max_lds, hipStream_t stream);
+                       int num_cu, int max_lds, hipStream_t stream);
 hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K,
                         const float* gpost, const uint64_t* cut, const uint8_t* flags, const float* ckpt, float* gw,
-                        int grid, int max_lds, hipStream_t stream);
+                        int num_cu, int max_lds, hipStream_t stream);
 
 // Small fill kernel (graph-capture safe replacement for hipMemsetAsync).
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream);

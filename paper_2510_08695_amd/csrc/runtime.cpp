@@ -1090,9 +1090,8 @@ bpdc_status bpdc_wms_forward(bpdc_plan p, int32_t code, const float* d_w, const 
   if (!d_w || !d_syn || !d_post || !d_cut || !d_flags) return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
     return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
-  const int grid = (int)std::min<int64_t>(B, (int64_t)p->num_cu * 8);
   HIP_TRY(bpdc::wms_forward(p->codes[code]->dev, p->kp, d_w, d_syn, B, shot_offset, K, d_post, d_cut, d_flags,
-                            (float*)d_ckpt, grid, p->max_lds, (hipStream_t)stream));
+                            (float*)d_ckpt, p->num_cu, p->max_lds, (hipStream_t)stream));
   return BPDC_OK;
 }
 
@@ -1106,9 +1105,8 @@ bpdc_status bpdc_wms_backward(bpdc_plan p, int32_t code, const float* d_w, const
     return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
     return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
-  const int grid = (int)std::min<int64_t>(B, (int64_t)p->num_cu * 4);
   HIP_TRY(bpdc::wms_backward(p->codes[code]->dev, p->kp, d_w, d_syn, B, K, d_grad_post, d_cut, d_flags,
-                             (const float*)d_ckpt, d_grad_w, grid, p->max_lds, (hipStream_t)stream));
+                             (const float*)d_ckpt, d_grad_w, p->num_cu, p->max_lds, (hipStream_t)stream));
   return BPDC_OK;
 }
 

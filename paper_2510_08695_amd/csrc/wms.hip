@@ -18,6 +18,9 @@
 // posteriors.  One workgroup per shot; messages of a segment live in LDS;
 // per-edge weight gradients are summed in LDS and added to the output once
 // per workgroup.
+#include <algorithm>
+#include <cstdlib>
+
 #include "internal.h"
 // after the HIP runtime header: bpdc_device.h itself includes nothing
 #include "bpdc_device.h"
@@ -275,7 +278,8 @@ __global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, c
               const float mag = (e == a1) ? m2 : m1;
               const int src = (e == a1) ? a2 : a1;
               const float sig = (neg ^ ((qp[e] < 0.0f) ? 1u : 0u)) ? -1.0f : 1.0f;
-              atomicAdd(&gw[(size_t)pass * E + e], g * sig * mag);
+              // edge e belongs to this thread's check only: a plain add
+              gw[(size_t)pass * E + e] += g * sig * mag;
               if (src >= 0) gqn[src] += g * sig * wp[e] * sgnf(qp[src]);
             }
           }
@@ -318,30 +322,55 @@ size_t wms_backward_lds(const DevCode& d, int K) {
          16;
 }
 
+// Threads per workgroup of the weighted kernels (one workgroup per shot; 64,
+// 128 or 256): the forward kernel's small LDS footprint lets one-wave
+// workgroups fill the compute units (64, measured fastest on BB144); the
+// adjoint keeps K + 1 message vectors per shot and is LDS-bound, so it takes
+// two waves per shot (128).  BPDC_WMS_THREADS_FWD / _BWD override.
+int wms_threads(bool backward) {
+  const char* e = getenv(backward ? "BPDC_WMS_THREADS_BWD" : "BPDC_WMS_THREADS_FWD");
+  const int v = e ? atoi(e) : (backward ? 128 : 64);
+  return v <= 64 ? 64 : (v <= 128 ? 128 : 256);
+}
+
+// Persistent grid: as many workgroups as fit on the device at once, at most B.
+int wms_grid(const void* kernel, int threads, size_t lds, int num_cu, int64_t B) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)nb * num_cu));
+}
+
 hipError_t wms_forward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B,
                        int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, float* ckpt,
-                       int grid, int max_lds, hipStream_t stream) {
+                       int num_cu, int max_lds, hipStream_t stream) {
   const size_t lds = wms_forward_lds(d);
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)k_wms_forward, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
   (void)hipGetLastError();
+  const int threads = wms_threads(false);
+  const int grid = wms_grid((const void*)k_wms_forward, threads, lds, num_cu, B);
   const int nck1 = (p.T1 + K - 1) / K, nck2 = (p.T2 + K - 1) / K;
-  hipLaunchKernelGGL(k_wms_forward, dim3(grid), dim3(256), lds, stream, wcode(d), w, syn, B, shot_offset, K, nck1,
+  hipLaunchKernelGGL(k_wms_forward, dim3(grid), dim3(threads), lds, stream, wcode(d), w, syn, B, shot_offset, K, nck1,
                      nck2, post, cut, flags, ckpt, p);
   return hipGetLastError();
 }
 
 hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K,
                         const float* gpost, const uint64_t* cut, const uint8_t* flags, const float* ckpt, float* gw,
-                        int grid, int max_lds, hipStream_t stream) {
+                        int num_cu, int max_lds, hipStream_t stream) {
   const size_t lds = wms_backward_lds(d, K);
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)k_wms_backward, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
   (void)hipGetLastError();
+  const int threads = wms_threads(true);
+  const int grid = wms_grid((const void*)k_wms_backward, threads, lds, num_cu, B);
   const int nck1 = (p.T1 + K - 1) / K, nck2 = (p.T2 + K - 1) / K;
-  hipLaunchKernelGGL(k_wms_backward, dim3(grid), dim3(256), lds, stream, wcode(d), w, syn, B, K, nck1, nck2, gpost,
+  hipLaunchKernelGGL(k_wms_backward, dim3(grid), dim3(threads), lds, stream, wcode(d), w, syn, B, K, nck1, nck2, gpost,
                      cut, flags, ckpt, gw, p);
   return hipGetLastError();
 }
