@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, c
   float* qs = (float*)smem;          // [(K + 1) * E] messages q(t0 .. t0 + K)
   float* r = qs + (size_t)(K + 1) * E;  // [E] r(t) (recomputed)
   float* gq = r + E;                 // [E] dLoss/dq(t)
-  float* gqn = gq + E;               // [E] dLoss/dq(t - 1) being accumulated
+  float* gqn = gq + E;               // [E] dLoss/dq(t - 1) being accumulated (the two swap roles)
   float* gr = gqn + E;               // [E] dLoss/dr(t)
   float* gw = gr + E;                // [2 * E] per-workgroup weight gradients
   float* L = gw + 2 * E;             // [n]
@@ -284,8 +284,11 @@ __global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, c
             }
           }
           __syncthreads();
-          for (int e = threadIdx.x; e < E; e += blockDim.x) gq[e] = gqn[e];
-          __syncthreads();
+          // dLoss/dq(t - 1) becomes the next step's dLoss/dq(t); the old buffer
+          // is cleared before it accumulates again
+          float* tmp = gq;
+          gq = gqn;
+          gqn = tmp;
         }
       }
     }
