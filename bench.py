@@ -39,6 +39,7 @@ COUNTERS = {
     "surface7": (LANE_SOURCES, "profiles/bpdc_lane_kernel_surface7_ps_p001_1e6.md"),
     "circuit": (GROUP_SOURCES, "profiles/k_group_circuit_bb144_T12_p0001_2e4.md"),
     "soft": (LANE_SOURCES, "profiles/bpdc_lane_kernel_soft_bb144_p005_1e6.md"),
+    "toric6ps": (GROUP_SOURCES, "profiles/k_group_ps_toric6_p005_1e6.md"),
 }
 
 
@@ -468,7 +469,8 @@ def run_toric6ps(args):
                    rule=P.RULE_PRODUCT_SUM)
     B = args.shots
     res = _single(args, code, B, 11, prm, f"toric L=6 code capacity p=0.05, {B} shots, product-sum, T=72+72, "
-                  "posterior second pass", "shots/s BP+DC product-sum toric L=6 p=0.05", P.KERNEL_GROUP)
+                  "posterior second pass", "shots/s BP+DC product-sum toric L=6 p=0.05", P.KERNEL_GROUP,
+                  traffic_key="toric6ps" if B == 1_000_000 else None)
     print(json.dumps(res), flush=True)
 
 def run_phen(args):
