@@ -104,8 +104,8 @@ typedef struct {
    * e^-soft_shift; messages carry on.  The DC after a failed first pass and
    * the second pass are unchanged (the channel second-pass prior is the
    * unshifted one).  All three kernel families with min-sum (the lane family
-   * as its own code-specialised variant), the plain family with product-sum;
-   * weighted decoding returns BPDC_ERR_UNSUPPORTED. */
+   * as its own code-specialised variant), the group and plain families with
+   * product-sum; weighted decoding returns BPDC_ERR_UNSUPPORTED. */
   int32_t soft_period;
   float soft_shift;
 } bpdc_params;

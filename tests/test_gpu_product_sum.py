@@ -75,6 +75,10 @@ def test_product_sum_vs_float64_oracle(P, kname, name, p, shots, T):
                    rule=P.RULE_PRODUCT_SUM)
     plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
     g = gpu_decode(plan, code, sh.syndromes)
+    _check_vs_float64_oracle(P, code, sh, prm, g, shots)
+
+
+def _check_vs_float64_oracle(P, code, sh, prm, g, shots):
     ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "posterior"), precision="f64")
     # decisions on shots with clear margins
     sel = ref["margin"] >= 1e-3
@@ -99,6 +103,33 @@ def test_product_sum_vs_float64_oracle(P, kname, name, p, shots, T):
     assert np.isinf(g["post"][cut]).all() and (g["post"][cut] > 0).all()
     assert not cut[(g["flags"] & 2) == 0].any()
     np.testing.assert_array_equal(g["ehat"].astype(bool), g["post"] <= 0)
+    return ref
+
+
+@pytest.mark.parametrize("name,p,shots,T", [("surface5", 0.03, 4000, 25), ("toric6", 0.05, 3000, 50)])
+def test_product_sum_soft_dc(P, name, p, shots, T):
+    """Product-sum with intermittent soft DC (K = 5, beta = 0.5) on the plain and
+    group kernels: the float64 oracle's bar above, and the group kernel's outputs
+    equal to the plain kernel's bit for bit."""
+    code = _code(name, p)
+    sh = synth.make_shots(code, shots, 7000 + shots)
+    prm = P.Params(max_iter=(T, T), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=31,
+                   rule=P.RULE_PRODUCT_SUM, soft_period=5, soft_shift=0.5)
+    c = P.Code.from_problem(code)
+    print(f"case {name} p={p} product-sum soft DC", flush=True)
+    a = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_PLAIN), code, sh.syndromes)
+    ref = _check_vs_float64_oracle(P, code, sh, prm, a, shots)
+    assert (((ref["flags"] & 2) != 0) | (ref["iters"][:, 0] > 5)).sum() > 0
+    b = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_GROUP), code, sh.syndromes)
+    for k in ("flags", "iters", "ehat", "cut"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
+    # soft DC changed the decoding
+    off = oracle.decode(code, sh.syndromes, oracle_params(P.Params(max_iter=(T, T), alpha=1.0,
+                                                                   second_pass_prior=P.PRIOR_POSTERIOR, seed=31,
+                                                                   rule=P.RULE_PRODUCT_SUM), "posterior"),
+                        precision="f64", want_post=False)
+    assert (off["iters"] != ref["iters"]).any()
 
 
 @pytest.mark.parametrize("name,p,shots,T", CASES)

@@ -62,13 +62,19 @@ def test_soft_dc_plans(P):
     code = P.Code.from_problem(synth.bb_code("bb144", p=0.05))
     prm = P.Params(max_iter=(50, 50), soft_period=5, soft_shift=0.5)
     assert P.Plan([code], prm, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_LANE
-    # product-sum with soft DC: plain only
+    # product-sum with soft DC: the group kernel (rows of at most 8 edges), else plain;
+    # the lane family has no product-sum soft variant
     surf = P.Code.from_problem(synth.rotated_surface_code(5, p=0.03))
     ps = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM,
                   soft_period=5, soft_shift=0.5)
-    assert P.Plan([surf], ps, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
+    assert P.Plan([surf], ps, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_GROUP
     with pytest.raises(P.BpdcError):
         P.Plan([surf], ps, kernel=P.KERNEL_LANE)
+    wide = P.Code.from_problem(synth.hgp_code(synth.random_regular_classical(12, 5, dv=3, dc=6),
+                                              with_logicals=False, p=0.03))
+    psc = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_CHANNEL, rule=P.RULE_PRODUCT_SUM,
+                   soft_period=5, soft_shift=0.5)
+    assert P.Plan([wide], psc, kernel=P.KERNEL_AUTO).info(0)["kernel"] == P.KERNEL_PLAIN
     for bad in (dict(soft_period=-1), dict(soft_period=5, soft_shift=-1.0), dict(soft_period=5, soft_shift=float("inf"))):
         with pytest.raises(P.BpdcError):
             P.Plan([code], P.Params(max_iter=(50, 50), **bad), kernel=P.KERNEL_GROUP)
