@@ -40,6 +40,7 @@ struct GCode {
                          // padded with check m (a dummy whose messages are -0)
   const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; padded with column n
                          // (a dummy whose posterior is +inf)
+  const int32_t* v_blk_deg;  // [ceil(n/64)]: largest column degree of each block of 64 columns
   int max_col_deg, max_row_deg;
 };
 
@@ -188,6 +189,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // with the posterior prior
     float* lam2 = (float*)(synw + ((m + 31) >> 5));
     const bool soft = P.soft_period > 0;
+    // the 64-bit-record variant (rows above 32 edges: circuit-level DEMs, whose
+    // column degrees differ from block to block) bounds each wave's column
+    // chunks by its block's largest degree; the 32-bit variant keeps the
+    // code's (fewer registers live)
+    const bool blk_deg = Wide && (nt & 63) == 0;
     // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
     // padded row entry reads L = +inf, so q saturates at lsat: it is never a
     // new minimum, leaves the second minimum (a median with lsat) and the
@@ -227,9 +233,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
           } else if (Lv != INF) {
             // entries in chunks of 4, all loads of a chunk issued before the sums;
-            // padding entries read the dummy check and add -0
+            // padding entries read the dummy check and add -0.  A wave holds 64
+            // consecutive columns (v = tid + k nt with nt a multiple of 64), so
+            // it can stop at the largest degree of its block (a wave-uniform
+            // bound) instead of the code's
             const int pad = m << 6;
-            for (int k0 = 0; k0 < C.max_col_deg; k0 += 4) {
+            const int kend = blk_deg ? __builtin_amdgcn_readfirstlane(gload(C.v_blk_deg, v >> 6)) : C.max_col_deg;
+            for (int k0 = 0; k0 < kend; k0 += 4) {
               int ent[4];
 #pragma unroll
               for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : pad;

@@ -27,6 +27,7 @@ struct DevCode {
   float* lam = nullptr;          // [n]
   int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 6 | position in row), ascending rows; pad m << 6
   int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; pad n
+  int32_t* v_blk_deg = nullptr;  // [ceil(n/64)] largest column degree of each block of 64 columns
 };
 
 // Runtime decoder parameters as the kernels see them.
@@ -96,6 +97,7 @@ struct GCodeHost {
   const float* lam;
   const int32_t* v_ell;
   const int32_t* c_ell;
+  const int32_t* v_blk_deg;
   int max_col_deg, max_row_deg;
 };
 

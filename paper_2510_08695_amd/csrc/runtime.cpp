@@ -550,7 +550,7 @@ bpdc_status build_code_table(bpdc_plan_s* p) {
   for (size_t i = 0; i < p->codes.size(); ++i) {
     const bpdc::DevCode& d = p->codes[i]->dev;
     tab[i] = {d.n, d.m, d.md, p->kp.second_pass_posterior, d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge,
-              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam, d.v_ell, d.c_ell, d.max_col_deg, d.max_row_deg};
+              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam, d.v_ell, d.c_ell, d.v_blk_deg, d.max_col_deg, d.max_row_deg};
     rank[i] = (int32_t)i;
   }
   std::stable_sort(rank.begin(), rank.end(),
@@ -670,13 +670,16 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
     }
   for (int r = 0; r < g.m; ++r)
     for (int k = hrp[r]; k < hrp[r + 1]; ++k) cell[(size_t)(k - hrp[r]) * g.m + r] = hci[k];
+  std::vector<int32_t> vblk((size_t)std::max(1, (g.n + 63) / 64), 0);
+  for (int v = 0; v < g.n; ++v) vblk[v >> 6] = std::max(vblk[v >> 6], cp[v + 1] - cp[v]);
   if (hipGetDevice(&c->device) != hipSuccess) return fail(BPDC_ERR_HIP, "no HIP device");
   hipError_t e;
   if ((e = upload(&d.h_row_ptr, hrp)) != hipSuccess || (e = upload(&d.h_col, hci)) != hipSuccess ||
       (e = upload(&d.h_col_ptr, cp)) != hipSuccess || (e = upload(&d.h_col_edge, ce)) != hipSuccess ||
       (e = upload(&d.h_edge_row, er)) != hipSuccess || (e = upload(&d.d_row_ptr, drp)) != hipSuccess ||
       (e = upload(&d.d_col, dci)) != hipSuccess || (e = upload(&d.lam, c->lam)) != hipSuccess ||
-      (e = upload(&d.v_ell, vell)) != hipSuccess || (e = upload(&d.c_ell, cell)) != hipSuccess) {
+      (e = upload(&d.v_ell, vell)) != hipSuccess || (e = upload(&d.c_ell, cell)) != hipSuccess ||
+      (e = upload(&d.v_blk_deg, vblk)) != hipSuccess) {
     bpdc_code_destroy(c.release());
     return fail(e == hipErrorOutOfMemory ? BPDC_ERR_OOM : BPDC_ERR_HIP, "upload: %s", hipGetErrorString(e));
   }
@@ -688,7 +691,7 @@ bpdc_status bpdc_code_destroy(bpdc_code c) {
   if (!c) return BPDC_OK;
   bpdc::DevCode& d = c->dev;
   void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row,
-                  d.d_row_ptr, d.d_col,     d.lam,       d.v_ell,      d.c_ell};
+                  d.d_row_ptr, d.d_col,     d.lam,       d.v_ell,      d.c_ell, d.v_blk_deg};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
