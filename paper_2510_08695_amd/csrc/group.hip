@@ -324,6 +324,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             u32 sbc = 0u;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
+              // slots past the code's largest row degree hold padding in every
+              // row: skipped on a uniform (scalar) branch
+              if (k0 + j >= C.max_row_deg) break;
               const float Lv = Lj[j];
               parw ^= __float_as_uint(Lv) - 1u;
               // r_old: alpha * (min2 on the old argmin, min1 elsewhere) with its
