@@ -31,6 +31,7 @@ OPS_PER_DC_ENTRY = 2                # per nonzero of D on shots that run DC
 LANE_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/lane_kernel.hip",
                 "paper_2510_08695_amd/csrc/lane_spec.cpp")
 GROUP_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/group.hip")
+WMS_SOURCES = ("paper_2510_08695_amd/csrc/bpdc_device.h", "paper_2510_08695_amd/csrc/wms.hip")
 # committed rocprofv3 counter summaries of the dominant kernel of each workload at its default size
 COUNTERS = {
     "bb144": (LANE_SOURCES, "profiles/bpdc_lane_kernel_bb144_p005_1e6_counters.md"),
@@ -40,6 +41,7 @@ COUNTERS = {
     "circuit": (GROUP_SOURCES, "profiles/k_group_circuit_bb144_T12_p0001_2e4.md"),
     "soft": (LANE_SOURCES, "profiles/bpdc_lane_kernel_soft_bb144_p005_1e6.md"),
     "toric6ps": (GROUP_SOURCES, "profiles/k_group_ps_toric6_p005_1e6.md"),
+    "wms": (WMS_SOURCES, "profiles/k_wms_backward_bb144_65536.md"),
 }
 
 
@@ -657,7 +659,8 @@ def run_wms(args):
                         "frac": ops_k / (ms_b / 1e3) / PEAK_LANE_OPS}}
     dom_ms = max(ms_f, ms_b)
     roof = {"bound": "alu", "achieved": ops_k / (dom_ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "Tlane-op/s", "frac": ops_k / (dom_ms / 1e3) / PEAK_LANE_OPS, "traffic": None,
+            "unit": "Tlane-op/s", "frac": ops_k / (dom_ms / 1e3) / PEAK_LANE_OPS,
+            "traffic": committed_traffic("wms") if ms_b >= ms_f else None,
             "traffic_unit": "bytes per launch", "launch_ms": dom_ms, "ops_per_launch": ops_k,
             "kernel": "adjoint" if ms_b >= ms_f else "forward"}
     del fwd, gp
