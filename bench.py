@@ -42,6 +42,7 @@ COUNTERS = {
     "soft": (LANE_SOURCES, "profiles/bpdc_lane_kernel_soft_bb144_p005_1e6.md"),
     "toric6ps": (GROUP_SOURCES, "profiles/k_group_ps_toric6_p005_1e6.md"),
     "wms": (WMS_SOURCES, "profiles/k_wms_backward_bb144_65536.md"),
+    "toric6": (LANE_SOURCES, "profiles/bpdc_lane_kernel_toric6_p005_1e4.md"),
 }
 
 
@@ -383,7 +384,8 @@ def run_toric6(args):
     code = synth.toric_code(6, p=0.05)
     prm = P.Params(max_iter=(50, 50), alpha=0.625, second_pass_prior=P.PRIOR_POSTERIOR, seed=1)
     res = _single(args, code, 10_000, 1, prm, "toric L=6 code capacity p=0.05, 1e4 shots, alpha=0.625, "
-                  "T=50+50, posterior second pass", "shots/s BP+DC toric L=6 p=0.05", P.KERNEL_LANE)
+                  "T=50+50, posterior second pass", "shots/s BP+DC toric L=6 p=0.05", P.KERNEL_LANE,
+                  traffic_key="toric6")
     print(json.dumps(res), flush=True)
 
 
