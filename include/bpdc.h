@@ -178,7 +178,12 @@ bpdc_status bpdc_decode(bpdc_plan plan, int32_t code, const uint64_t* d_syn, int
  * launch.  Shot b belongs to code d_code_of_shot[b]; its syndrome starts at
  * word d_syn_off[b] of d_syn and its correction at word d_corr_off[b] of d_corr.
  * d_flags [B], d_iters [B][2] (optional) as in bpdc_decode.  The tie-break
- * counter of shot b is shot_offset + b. */
+ * counter of shot b is shot_offset + b.  The code indices are read on the
+ * device, so they cannot be validated before the launch: a shot whose index
+ * lies outside [0, ncodes) is skipped, its flags byte is set to
+ * BPDC_FLAG_BAD_CODE and its correction and iteration counts are left
+ * unwritten (its syndrome and correction offsets are never read). */
+#define BPDC_FLAG_BAD_CODE 0x80
 bpdc_status bpdc_decode_multi(bpdc_plan plan, const int32_t* d_code_of_shot, const uint64_t* d_syn,
                               const int64_t* d_syn_off, uint64_t* d_corr, const int64_t* d_corr_off,
                               uint8_t* d_flags, int16_t* d_iters, int64_t B, int64_t shot_offset,

@@ -8,8 +8,9 @@ the library has not been built.
 """
 from ._lib import (BpdcError, Params, Code, Plan, lib, lib_path, lane_precompile, weighted_bpdc,
                    KERNEL_AUTO, KERNEL_PLAIN, KERNEL_LANE, KERNEL_GROUP,
-                   PRIOR_CHANNEL, PRIOR_POSTERIOR, TIE_HASH, TIE_LOWEST_INDEX, RULE_MIN_SUM, RULE_PRODUCT_SUM)
+                   PRIOR_CHANNEL, PRIOR_POSTERIOR, TIE_HASH, TIE_LOWEST_INDEX, RULE_MIN_SUM, RULE_PRODUCT_SUM, FLAG_BAD_CODE)
 
 __all__ = ["BpdcError", "Params", "Code", "Plan", "lib", "lib_path", "lane_precompile", "weighted_bpdc",
            "KERNEL_AUTO", "KERNEL_PLAIN", "KERNEL_LANE", "KERNEL_GROUP",
-           "PRIOR_CHANNEL", "PRIOR_POSTERIOR", "TIE_HASH", "TIE_LOWEST_INDEX", "RULE_MIN_SUM", "RULE_PRODUCT_SUM"]
+           "PRIOR_CHANNEL", "PRIOR_POSTERIOR", "TIE_HASH", "TIE_LOWEST_INDEX", "RULE_MIN_SUM", "RULE_PRODUCT_SUM",
+           "FLAG_BAD_CODE"]

@@ -20,6 +20,7 @@ KERNEL_AUTO, KERNEL_PLAIN, KERNEL_LANE, KERNEL_GROUP = 0, 1, 2, 3
 PRIOR_CHANNEL, PRIOR_POSTERIOR = 0, 1
 TIE_HASH, TIE_LOWEST_INDEX = 0, 1
 RULE_MIN_SUM, RULE_PRODUCT_SUM = 0, 1
+FLAG_BAD_CODE = 0x80  # multi-code shot whose code index is out of range (skipped)
 
 EXPORTS = [
     "bpdc_code_create", "bpdc_code_destroy", "bpdc_code_info", "bpdc_plan_create",

@@ -64,6 +64,7 @@ struct GArgs {
   int64_t B;
   int64_t shot_offset;
   unsigned long long* queue;
+  const unsigned* n_bad;        // multi-code: shots with an out-of-range code index (kept out of `order`)
   KParams p;
 };
 
@@ -165,12 +166,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
   using Rec = CheckRec<Wide>;
   using W = typename Rec::Word;
 
+  // shots of a mixed batch whose code index is out of range were flagged by the
+  // ordering kernels and left out of `order`, which lists the others first
+  const long long nshots = a.n_bad ? a.B - (long long)*a.n_bad : a.B;
   for (;;) {
     if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
     __syncthreads();
     const long long idx = sIdx;
     __syncthreads();
-    if (idx >= a.B) break;
+    if (idx >= nshots) break;
     const long long b = a.order ? (long long)a.order[idx] : idx;
     const int ci = a.code_of_shot ? a.code_of_shot[b] : 0;
     const GCode C = a.codes[ci];
@@ -431,13 +435,19 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
 
 // Processing order of a mixed batch: shots grouped by code, codes by
 // descending column count (counting sort; order within a code is arbitrary,
-// results do not depend on it).
-__global__ void k_order_hist(const int32_t* code_of_shot, int64_t B, unsigned* hist) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < B) atomicAdd(&hist[code_of_shot[i]], 1u);
+// results do not depend on it).  A code index outside [0, ncodes) counts in
+// the extra bucket ncodes: such a shot gets the flags value kFlagBadCode here
+// and no place in the order, and the decode kernel stops after the others
+// (a skip inside its loop would put a thread-0 branch between barriers).
+__device__ __forceinline__ int order_bucket(const int32_t* code_of_shot, int64_t i, int ncodes) {
+  const int c = code_of_shot[i];
+  return ((unsigned)c < (unsigned)ncodes) ? c : ncodes;
 }
-__global__ void k_order_scan(const int32_t* rank_of_code, const int32_t* code_by_rank, int ncodes,
-                             const unsigned* hist, unsigned* base) {
+__global__ void k_order_hist(const int32_t* code_of_shot, int64_t B, int ncodes, unsigned* hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < B) atomicAdd(&hist[order_bucket(code_of_shot, i, ncodes)], 1u);
+}
+__global__ void k_order_scan(const int32_t* code_by_rank, int ncodes, const unsigned* hist, unsigned* base) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   unsigned s = 0;
   for (int r = 0; r < ncodes; ++r) {
@@ -445,11 +455,14 @@ __global__ void k_order_scan(const int32_t* rank_of_code, const int32_t* code_by
     base[c] = s;
     s += hist[c];
   }
-  (void)rank_of_code;
 }
-__global__ void k_order_scatter(const int32_t* code_of_shot, int64_t B, unsigned* base, int32_t* order) {
+__global__ void k_order_scatter(const int32_t* code_of_shot, int64_t B, int ncodes, unsigned* base,
+                                int32_t* order, uint8_t* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < B) order[atomicAdd(&base[code_of_shot[i]], 1u)] = (int32_t)i;
+  if (i >= B) return;
+  const int c = order_bucket(code_of_shot, i, ncodes);
+  if (c == ncodes) flags[i] = kFlagBadCode;
+  else order[atomicAdd(&base[c], 1u)] = (int32_t)i;
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {
@@ -468,14 +481,15 @@ size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edge
   return head + words * 4 + 16;
 }
 
-hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
-                        const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
+hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_t* code_of_shot,
+                        const int32_t* order, const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
                         size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream) {
   GArgs a;
   a.codes = (const GCode*)d_codes;
   a.code_of_shot = code_of_shot;
+  a.n_bad = n_bad;
   a.order = order;
   a.syn = syn;
   a.syn_off = syn_off;
@@ -529,13 +543,14 @@ int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds) {
 }
 
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,
-                       unsigned* hist, unsigned* base, int32_t* order, hipStream_t stream) {
-  hipLaunchKernelGGL(k_zero_u32, dim3((ncodes + 255) / 256), dim3(256), 0, stream, hist, ncodes);
+                       unsigned* hist, unsigned* base, int32_t* order, uint8_t* flags, hipStream_t stream) {
+  // hist and base hold ncodes + 1 buckets (the last one: out-of-range code indices)
+  hipLaunchKernelGGL(k_zero_u32, dim3((ncodes + 1 + 255) / 256), dim3(256), 0, stream, hist, ncodes + 1);
   const unsigned g = (unsigned)((B + 255) / 256);
-  if (B > 0) hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, stream, code_of_shot, B, hist);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, stream, (const int32_t*)nullptr, code_by_rank, ncodes,
-                     hist, base);
-  if (B > 0) hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, stream, code_of_shot, B, base, order);
+  if (B > 0) hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, stream, code_of_shot, B, ncodes, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, stream, code_by_rank, ncodes, hist, base);
+  if (B > 0)
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, stream, code_of_shot, B, ncodes, base, order, flags);
   return hipGetLastError();
 }
 

@@ -75,13 +75,20 @@ struct GroupTile {
 // the shot's state in dynamic LDS; also the multi-code launch.
 size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edges);
 int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds);
-hipError_t group_launch(const void* d_codes, const int32_t* code_of_shot, const int32_t* order,
-                        const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
+// Flags value of a multi-code shot whose code index is outside [0, ncodes): the
+// shot is skipped and nothing else of it is written.
+constexpr uint8_t kFlagBadCode = 0x80;
+// n_bad (device word, multi-code only, else null): the shots group_order left out of
+// `order`; the kernel decodes the first B - *n_bad entries of the order.
+hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_t* code_of_shot,
+                        const int32_t* order, const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
                         size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream);
+// hist and base hold ncodes + 1 entries each; hist[ncodes] counts the shots with an
+// out-of-range code index, which get flags kFlagBadCode and no place in `order`.
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,
-                       unsigned* hist, unsigned* base, int32_t* order, hipStream_t stream);
+                       unsigned* hist, unsigned* base, int32_t* order, uint8_t* flags, hipStream_t stream);
 
 // Mirror of the device code descriptor used by group.hip.
 struct GCodeHost {

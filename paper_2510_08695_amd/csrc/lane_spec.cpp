@@ -333,7 +333,10 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
       o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
       for (int j = 0; j < dv; ++j) {
         const int sl = e[j].slot, d = (int)g.rows[slot_base[sl]].size();
-        o << "{ const float q = L - r" << j << "; " << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << sl << ", ev); "
+        // q = sat(L - r) as Sec. II.C's product-sum takes it: unlike min-sum, tanh(|q| / 2)
+        // sees |q| itself, so a cut column (L = +inf) must send exactly +lsat and a
+        // posterior beyond lsat must be held there before tanh.
+        o << "{ const float q = bpdc_dev::sat(L - r" << j << ", LS); " << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << sl << ", ev); "
           << (pos[i][j] == 0 ? "NB_PSACC0(" : "NB_PSACC(") << sl << ", " << kk[j] << ", " << bb[j] << ", q); } \\\n";
         if (pos[i][j] == sdeg[sl] - 1) {
           // finalise check slot sl: d edges in registers rbase[sl] ..

@@ -474,7 +474,7 @@ float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, Tu
   float best = -1.0f;
   for (int rep = 0; rep < 2; ++rep) {
     (void)hipEventRecord(e0, 0);
-    hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
+    hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
                                       nullptr, nullptr, nullptr, S, 0, tile.threads, tile.grid, tile.lds_bytes,
                                       tile.info_bytes, tb.queue, 0);
     (void)hipEventRecord(e1, 0);
@@ -564,8 +564,11 @@ bpdc_status build_code_table(bpdc_plan_s* p) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Multi-code workspace: the shot counter, the per-code histogram and bases of
+// the ordering sort (one extra bucket each for out-of-range code indices), and
+// the processing order.
 size_t multi_ws_bytes(const bpdc_plan_s* p, int64_t B) {
-  return 256 + 2 * align256(p->codes.size() * 4) + align256((size_t)std::max<int64_t>(B, 1) * 4);
+  return 256 + 2 * align256((p->codes.size() + 1) * 4) + align256((size_t)std::max<int64_t>(B, 1) * 4);
 }
 
 bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* syn, const int64_t* syn_off,
@@ -574,10 +577,10 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
   char* w = (char*)ws;
   unsigned long long* queue = (unsigned long long*)w;
   unsigned* hist = (unsigned*)(w + 256);
-  unsigned* base = (unsigned*)(w + 256 + align256(p->codes.size() * 4));
-  int32_t* order = (int32_t*)(w + 256 + 2 * align256(p->codes.size() * 4));
-  HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, s));
-  HIP_TRY(bpdc::group_launch(p->d_code_table, cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
+  unsigned* base = (unsigned*)(w + 256 + align256((p->codes.size() + 1) * 4));
+  int32_t* order = (int32_t*)(w + 256 + 2 * align256((p->codes.size() + 1) * 4));
+  HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, flags, s));
+  HIP_TRY(bpdc::group_launch(p->d_code_table, hist + p->codes.size(), cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
                              nullptr, iters, B, shot_offset, p->multi_tile.threads, p->multi_tile.grid,
                              p->multi_tile.lds_bytes, p->multi_tile.info_bytes, queue, s));
   return BPDC_OK;
@@ -968,7 +971,7 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
       return lane_launch(p, cp, c, io, d_ws, s);
     case BPDC_KERNEL_GROUP: {
       const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
-      HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
+      HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
                                  d_cut, d_iters, B, shot_offset, cp.tile.threads, cp.tile.grid, cp.tile.lds_bytes,
                                  cp.tile.info_bytes, (unsigned long long*)d_ws, s));
       return BPDC_OK;

@@ -218,6 +218,9 @@ __global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, c
       const float* wp = w + (size_t)pass * E;
       const float* ck = ckpt + ((size_t)(pass ? B * nck1 : 0) + (size_t)b * nck[pass]) * E;
       const float* gp = gpost + ((size_t)pass * B + b) * n;
+      // a shot without DC reports its first-pass posteriors in both output rows,
+      // so pass 0 collects the gradient of both rows
+      const float* gp2 = dc ? nullptr : gpost + ((size_t)B + b) * n;
       for (int s = nck[pass] - 1; s >= 0; --s) {
         const int t0 = s * K, t1 = min(T, t0 + K);
         for (int e = threadIdx.x; e < E; e += blockDim.x) qs[e] = ck[(size_t)s * E + e];
@@ -241,7 +244,7 @@ __global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, c
             }
             float Lv = C.lam[v];
             for (int k = k0; k < k1; ++k) Lv = Lv + r[C.ce[k]];
-            float gL = (t == T && fabsf(Lv) < LS) ? gp[v] : 0.0f;
+            float gL = (t == T && fabsf(Lv) < LS) ? (gp2 ? gp[v] + gp2[v] : gp[v]) : 0.0f;
             for (int k = k0; k < k1; ++k) {
               const int e = C.ce[k];
               if (fabsf(Lv - r[e]) < LS) gL += gq[e];

@@ -11,7 +11,7 @@ of them is imported here.
 from .codes import (Csr, Code, toric_code, bb_code, hgp_code, random_regular_classical,
                     phenomenological_dem, hgp_batch_codes, repetition_cycle, rotated_surface_code,
                     rotated_surface_matrices)
-from .sample import (sample_errors, syndromes_of, pack_bits, unpack_bits, ShotSet, make_shots)
+from .sample import (sample_errors, syndromes_of, pack_bits, unpack_bits, ShotSet, make_shots, mixed_batch)
 from .f2 import f2_rank, logical_operators, residual_is_logical
 from .circuit import bb_circuit_dem, bb_circuit_matrices, bb_circuit_mechanisms
 
@@ -19,7 +19,7 @@ __all__ = [
     "Csr", "Code", "toric_code", "bb_code", "hgp_code", "random_regular_classical",
     "phenomenological_dem", "hgp_batch_codes", "repetition_cycle", "rotated_surface_code",
     "rotated_surface_matrices",
-    "sample_errors", "syndromes_of", "pack_bits", "unpack_bits", "ShotSet", "make_shots",
+    "sample_errors", "syndromes_of", "pack_bits", "unpack_bits", "ShotSet", "make_shots", "mixed_batch",
     "f2_rank", "logical_operators", "residual_is_logical",
     "bb_circuit_dem", "bb_circuit_matrices", "bb_circuit_mechanisms",
 ]

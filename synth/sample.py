@@ -69,3 +69,28 @@ def make_shots(code, shots: int, seed: int, priors: Optional[np.ndarray] = None)
     rng = np.random.default_rng(seed)
     e = sample_errors(rng, shots, code.priors if priors is None else priors)
     return ShotSet(e, syndromes_of(e, code.H), seed)
+
+
+def mixed_batch(codes, mean_shots: float, seed: int, shot_seed_base: int):
+    """A batch of shots over several codes in a seeded random global order.
+
+    Code i gets Poisson(mean_shots) shots (counts drawn from a generator seeded
+    with `seed`, which then shuffles the batch order); its shots are drawn with
+    seed shot_seed_base + i.  Returns (code_of_shot int32 [B], packed syndromes
+    as int64 words concatenated in batch order, per-code list of
+    (batch indices, ShotSet))."""
+    rng = np.random.default_rng(seed)
+    counts = rng.poisson(mean_shots, size=len(codes))
+    code_of_shot = np.concatenate([np.full(k, i, np.int32) for i, k in enumerate(counts)])
+    rng.shuffle(code_of_shot)
+    rows = [None] * len(code_of_shot)
+    per = []
+    for i, c in enumerate(codes):
+        idx = np.nonzero(code_of_shot == i)[0]
+        sh = make_shots(c, len(idx), shot_seed_base + i)
+        per.append((idx, sh))
+        packed = pack_bits(sh.syndromes)
+        for k, b in enumerate(idx):
+            rows[b] = packed[k]
+    syn = np.concatenate(rows).view(np.int64) if rows else np.zeros(0, np.int64)
+    return code_of_shot, syn, per

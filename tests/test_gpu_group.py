@@ -138,3 +138,41 @@ def test_multi_code_graph_replays(P):
         for a, b in zip(r, eager[0]):
             np.testing.assert_array_equal(a, b)
     _check_multi(P, prm, codes, per_code, eager[0], corr_off)
+
+
+def test_multi_code_out_of_range_index_is_flagged(P):
+    """A code index outside [0, ncodes) is read on the device only: that shot is skipped
+    with flags = FLAG_BAD_CODE, its correction words and iteration counts are left as they
+    were, and every other shot of the batch decodes exactly as before."""
+    import torch
+    codes = [_small_hgp(j, nc, p=0.05) for j, nc in enumerate([16, 20])]
+    counts = [50, 40]
+    prm = P.Params(max_iter=(30, 30), alpha=0.625, seed=4)
+    plan = P.Plan([P.Code.from_problem(c) for c in codes], prm, kernel=P.KERNEL_GROUP)
+    code_of_shot, syn, per_code = _mixed_batch(P, codes, counts, 70)
+    so, co, sw, nw = plan.multi_buffers(torch.from_numpy(code_of_shot).cuda())
+    bad = {3: -1, 17: 2, 51: 1 << 30}
+    cos_bad = code_of_shot.copy()
+    for b, v in bad.items():
+        cos_bad[b] = v
+    print("case multi-code with out-of-range indices", bad, flush=True)
+    corr = torch.full((nw,), -1, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(len(cos_bad), dtype=torch.uint8, device="cuda")
+    iters = torch.full((len(cos_bad), 2), -7, dtype=torch.int16, device="cuda")
+    plan.decode_multi(torch.from_numpy(cos_bad).cuda(), torch.from_numpy(syn).cuda(), so, corr, co, flags, iters)
+    torch.cuda.synchronize()
+    corr_h, flags_h, iters_h, co_h = (corr.cpu().numpy(), flags.cpu().numpy(), iters.cpu().numpy(),
+                                      co.cpu().numpy())
+    for b in bad:
+        assert flags_h[b] == P.FLAG_BAD_CODE
+        assert (iters_h[b] == -7).all()
+        nwb = (codes[code_of_shot[b]].n + 63) // 64
+        assert (corr_h[co_h[b]:co_h[b] + nwb] == -1).all()
+    good = np.ones(len(cos_bad), bool)
+    good[list(bad)] = False
+    assert (flags_h[good] & P.FLAG_BAD_CODE == 0).all()
+    for i, c in enumerate(codes):
+        idx, sh = per_code[i]
+        keep = [k for k, b in enumerate(idx) if good[b]]
+        per_code[i] = (idx[keep], synth.ShotSet(sh.errors[keep], sh.syndromes[keep], sh.seed))
+    _check_multi(P, prm, codes, per_code, (corr_h, flags_h, iters_h), co_h)

@@ -151,6 +151,29 @@ def test_product_sum_kernels_equal_bit_for_bit(P, name, p, shots, T):
         np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
 
 
+@pytest.mark.parametrize("name,p,shots,T", [("surface5", 0.03, 3000, 25), ("surface7", 0.01, 4000, 49)])
+def test_product_sum_low_saturation(P, name, p, shots, T):
+    """llr_sat = 8, below the level where float32 tanh(|q| / 2) reaches 1: messages from cut
+    columns (posterior +inf) and from columns whose posterior exceeds 8 must be held at 8
+    before tanh (q = sat(L - r), Sec. II.C), or they would send tanh = 1 instead of tanh(4).
+    The lane (surface codes), group and plain kernels agree bit for bit and meet the float64
+    oracle's product-sum bar at this saturation."""
+    code = _code(name, p)
+    sh = synth.make_shots(code, shots, 8000 + shots)
+    prm = P.Params(max_iter=(T, T), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=37,
+                   rule=P.RULE_PRODUCT_SUM, llr_sat=8.0)
+    c = P.Code.from_problem(code)
+    print(f"case {name} p={p} product-sum llr_sat=8", flush=True)
+    a = gpu_decode(P.Plan([c], prm, kernel=P.KERNEL_PLAIN), code, sh.syndromes)
+    ref = _check_vs_float64_oracle(P, code, sh, prm, a, shots)
+    assert ((ref["flags"] & 2) != 0).sum() > 10
+    for kid in _kernels(P, name)[1:]:
+        b = gpu_decode(P.Plan([c], prm, kernel=kid), code, sh.syndromes)
+        for k in ("flags", "iters", "ehat", "cut"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"kernel {kid} {k}")
+        np.testing.assert_array_equal(a["post"].view(np.uint32), b["post"].view(np.uint32))
+
+
 def test_product_sum_plans(P):
     prm = P.Params(max_iter=(25, 25), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, rule=P.RULE_PRODUCT_SUM)
     small = P.Code.from_problem(synth.rotated_surface_code(5, p=0.03))

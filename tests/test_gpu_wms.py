@@ -155,3 +155,61 @@ def test_autograd_function_and_training_step_reduce_loss(setup):
         opt.step()
         losses.append(loss.item())
     assert np.mean(losses[-3:]) < np.mean(losses[:3])
+
+
+def _loss_final(post2, errors, cut):
+    """Mean over shots of BCE(final posteriors, e) on the uncut columns, every shot included:
+    a shot without DC reports its first-pass posteriors in the final row, so this loss
+    reaches the first pass's scales through those shots."""
+    e = errors.astype(np.float64)
+    keep = cut == 0
+    L = np.where(keep, post2.astype(np.float64), 0.0)
+    bce = e * np.logaddexp(0, L) + (1 - e) * np.logaddexp(0, -L)
+    g = np.where(keep, 1.0 / (1.0 + np.exp(-L)) - (1 - e), 0.0) / e.shape[0]
+    return float((bce * keep).sum() / e.shape[0]), g
+
+
+def test_adjoint_of_a_loss_on_the_final_row_of_every_shot(setup):
+    import torch
+    P, code, prm, plan = setup
+    B = 192
+    shots = synth.make_shots(code, B, 5003)
+    E = code.H.nnz
+    rng = np.random.default_rng(3)
+    w = (0.625 + 0.05 * rng.standard_normal(2 * E)).astype(np.float32)
+    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w)
+    post = out["post"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    cut = synth.unpack_bits(out["cut"].cpu().numpy().view(np.uint64), code.n)
+    assert ((flags & 2) == 0).sum() > B // 2 and ((flags & 2) != 0).sum() > 5
+    _, g2 = _loss_final(post[1], shots.errors, cut)
+    gpost = np.stack([np.zeros_like(g2), g2]).astype(np.float32)
+    gw = plan.wms_backward(wt, syn, out, torch.from_numpy(gpost).cuda()).cpu().numpy()
+    op = oracle_params(prm, "channel")
+
+    def f64_loss(wv):
+        o = oracle.decode(code, shots.syndromes, op, precision="f64", weights=wv)
+        return _loss_final(o["post"], shots.errors, o["cut"])[0], o["cut"]
+
+    w64 = w.astype(np.float64)
+    base, base_cut = f64_loss(w64)
+    # first-pass scales (reached through the shots without DC) and second-pass scales
+    idx = np.concatenate([rng.choice(E, size=24, replace=False), E + rng.choice(E, size=12, replace=False)])
+    checked = [0, 0]
+    for j in idx:
+        h = 1e-4 * max(1.0, abs(w64[j]))
+        wp, wm = w64.copy(), w64.copy()
+        wp[j] += h
+        wm[j] -= h
+        lp, cp = f64_loss(wp)
+        lm, cm = f64_loss(wm)
+        if not ((cp == base_cut).all() and (cm == base_cut).all()):
+            continue
+        fwd, bwd = (lp - base) / h, (base - lm) / h
+        if abs(fwd - bwd) > 1e-3 * max(1e-3, abs(fwd) + abs(bwd)):
+            continue
+        fd = (lp - lm) / (2 * h)
+        assert abs(gw[j] - fd) <= 2e-3 * max(abs(fd), 1e-3), (j, gw[j], fd)
+        checked[int(j >= E)] += 1
+    assert checked[0] >= 12 and checked[1] >= 4, checked
+    assert np.abs(gw[:E]).max() > 0
