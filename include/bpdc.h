@@ -174,6 +174,24 @@ bpdc_status bpdc_decode(bpdc_plan plan, int32_t code, const uint64_t* d_syn, int
                         uint64_t* d_cut, int16_t* d_iters, void* d_ws, size_t ws_bytes,
                         void* stream);
 
+/* bpdc_decode for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that must not call hipMalloc):
+ * the same arguments without the workspace, which comes from a static
+ * device array of BPDC_NOALLOC_SCRATCH_BYTES bytes inside the library (each
+ * GPU the library runs on holds its own copy until the process ends).  The
+ * call allocates nothing.  A batch whose workspace (bpdc_workspace_size)
+ * exceeds BPDC_NOALLOC_SCRATCH_BYTES is refused with BPDC_ERR_WORKSPACE (a
+ * BB[[144,12,12]] plan on the lane family fits about 2e6 shots; the plain
+ * family needs about 8 E + 8 n bytes per shot).  Every call on one GPU uses
+ * that GPU's one array, whose contents persist from the previous call (the
+ * kernels clear what must start at zero), so calls that overlap in time on
+ * one GPU (two streams, two threads) race and must be serialised by the
+ * caller.  Results equal bpdc_decode's. */
+#define BPDC_NOALLOC_SCRATCH_BYTES (32u << 20)
+bpdc_status bpdc_decode_noalloc(bpdc_plan plan, int32_t code, const uint64_t* d_syn, int64_t B,
+                                int64_t shot_offset, uint64_t* d_corr, uint8_t* d_flags,
+                                float* d_post, uint64_t* d_cut, int16_t* d_iters, void* stream);
+
 /* Decode a mixed batch of B shots over all codes of the plan in one persistent
  * launch.  Shot b belongs to code d_code_of_shot[b]; its syndrome starts at
  * word d_syn_off[b] of d_syn and its correction at word d_corr_off[b] of d_corr.

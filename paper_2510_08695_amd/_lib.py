@@ -27,7 +27,7 @@ EXPORTS = [
     "bpdc_plan_destroy", "bpdc_plan_info", "bpdc_workspace_size", "bpdc_decode",
     "bpdc_decode_multi", "bpdc_graph_capture_multi", "bpdc_graph_launch",
     "bpdc_wms_ckpt_size", "bpdc_wms_forward", "bpdc_wms_backward", "bpdc_lane_precompile",
-    "bpdc_plan_set_dc_stats",
+    "bpdc_plan_set_dc_stats", "bpdc_decode_noalloc",
     "bpdc_status_string", "bpdc_last_error", "bpdc_version",
 ]
 
@@ -80,6 +80,7 @@ def lib():
             "bpdc_wms_backward": [P, I32, P, P, I64, I32, P, P, P, P, C.c_size_t, P, P],
             "bpdc_lane_precompile": [C.POINTER(_Csr), C.POINTER(_Csr), I32, I32, I32, I32],
             "bpdc_plan_set_dc_stats": [P, P, I64],
+            "bpdc_decode_noalloc": [P, I32, P, I64, I64, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -260,6 +261,31 @@ class Plan:
         _check(lib().bpdc_decode(self.handle, code, _ptr(syn), B, shot_offset, _ptr(out["corr"]),
                                  _ptr(out["flags"]), _ptr(out.get("post")), _ptr(out.get("cut")),
                                  _ptr(out.get("iters")), _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def decode_noalloc(self, syn, code: int = 0, shot_offset: int = 0, want_post: bool = False,
+                       want_cut: bool = False, want_iters: bool = False, out: Optional[dict] = None) -> dict:
+        """decode() through bpdc_decode_noalloc: no workspace, the library's static scratch.
+        With `out` given (all buffers preallocated) the call allocates nothing."""
+        import torch
+        c = self.codes[code]
+        B = syn.shape[0]
+        nw = (c.n + 63) // 64
+        assert syn.dtype == torch.int64 and syn.is_cuda and syn.shape[1] == (c.m + 63) // 64
+        assert syn.is_contiguous()
+        if out is None:
+            dev = syn.device
+            out = {"corr": torch.empty((B, nw), dtype=torch.int64, device=dev),
+                   "flags": torch.empty(B, dtype=torch.uint8, device=dev)}
+            if want_post:
+                out["post"] = torch.empty((B, c.n), dtype=torch.float32, device=dev)
+            if want_cut:
+                out["cut"] = torch.empty((B, nw), dtype=torch.int64, device=dev)
+            if want_iters:
+                out["iters"] = torch.empty((B, 2), dtype=torch.int16, device=dev)
+        _check(lib().bpdc_decode_noalloc(self.handle, code, _ptr(syn), B, shot_offset, _ptr(out["corr"]),
+                                         _ptr(out["flags"]), _ptr(out.get("post")), _ptr(out.get("cut")),
+                                         _ptr(out.get("iters")), _stream()))
         return out
 
     # ---- multi-code batch -------------------------------------------------------------

@@ -121,4 +121,8 @@ hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, cons
 // Small fill kernel (graph-capture safe replacement for hipMemsetAsync).
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream);
 
+// Device address of `device`'s copy of the static scratch of bpdc_decode_noalloc
+// (noalloc.hip); call with that device current.  Looked up once per device.
+hipError_t noalloc_scratch(int device, void** ptr);
+
 }  // namespace bpdc

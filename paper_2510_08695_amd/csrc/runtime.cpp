@@ -780,6 +780,11 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
   p->kp.soft_period = P.soft_period;
   p->kp.soft_shift = P.soft_period > 0 ? P.soft_shift : 0.0f;
   HIP_TRY(hipGetDevice(&p->device));
+  {  // set-up of bpdc_decode_noalloc on this device: the static scratch's device address, once per
+     // device (a failure is reported by bpdc_decode_noalloc itself, which looks it up again)
+    void* scratch = nullptr;
+    if (bpdc::noalloc_scratch(p->device, &scratch) != hipSuccess) (void)hipGetLastError();
+  }
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->num_cu = prop.multiProcessorCount;
@@ -979,6 +984,29 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
     default:
       return fail(BPDC_ERR_UNSUPPORTED, "kernel family not available");
   }
+}
+
+bpdc_status bpdc_decode_noalloc(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_t B,
+                                int64_t shot_offset, uint64_t* d_corr, uint8_t* d_flags, float* d_post,
+                                uint64_t* d_cut, int16_t* d_iters, void* stream) {
+  if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
+  if (code < 0 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad code index");
+  if (B < 0 || shot_offset < 0) return fail(BPDC_ERR_INVALID_ARG, "negative batch or offset");
+  size_t need = 0;
+  bpdc_status st = bpdc_workspace_size(p, code, B, &need);
+  if (st != BPDC_OK) return st;
+  if (need > (size_t)BPDC_NOALLOC_SCRATCH_BYTES)
+    return fail(BPDC_ERR_WORKSPACE,
+                "a batch of %lld shots needs %zu bytes of workspace, above the %zu-byte static scratch of "
+                "bpdc_decode_noalloc: decode it in smaller batches or pass a workspace to bpdc_decode",
+                (long long)B, need, (size_t)BPDC_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(BPDC_ERR_INVALID_ARG, "plan was created on device %d, current is %d", p->device, dev);
+  void* ws = nullptr;
+  HIP_TRY(bpdc::noalloc_scratch(dev, &ws));
+  return bpdc_decode(p, code, d_syn, B, shot_offset, d_corr, d_flags, d_post, d_cut, d_iters, ws,
+                     (size_t)BPDC_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 bpdc_status bpdc_decode_multi(bpdc_plan p, const int32_t* d_code_of_shot, const uint64_t* d_syn,
