@@ -108,14 +108,17 @@ struct GCodeHost {
   int max_col_deg, max_row_deg;
 };
 
-// Weighted min-sum forward (checkpointed) and adjoint (wms.hip).
+// Weighted min-sum forward (checkpointed) and adjoint (wms.hip).  Rows of at
+// most kWmsMaxRowDeg edges (the sign bits of a 12-byte check state).
+constexpr int kWmsMaxRowDeg = 21;
+size_t wms_ckpt_bytes(const DevCode& d, const KParams& p, int64_t B, int K);
 size_t wms_forward_lds(const DevCode& d);
 size_t wms_backward_lds(const DevCode& d, int K);
 hipError_t wms_forward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B,
-                       int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, float* ckpt,
+                       int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, void* ckpt,
                        int num_cu, int max_lds, hipStream_t stream);
 hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K,
-                        const float* gpost, const uint64_t* cut, const uint8_t* flags, const float* ckpt, float* gw,
+                        const float* gpost, const uint64_t* cut, const uint8_t* flags, const void* ckpt, float* gw,
                         int num_cu, int max_lds, hipStream_t stream);
 
 // Small fill kernel (graph-capture safe replacement for hipMemsetAsync).

@@ -1095,15 +1095,16 @@ static bpdc_status wms_check(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
   if (p->kp.rule != BPDC_RULE_MIN_SUM) return fail(BPDC_ERR_UNSUPPORTED, "weighted decoding is min-sum only");
   if (p->kp.soft_period > 0) return fail(BPDC_ERR_UNSUPPORTED, "weighted decoding has no soft DC");
   const bpdc::DevCode& d = p->codes[code]->dev;
+  if (d.max_row_deg > bpdc::kWmsMaxRowDeg)
+    return fail(BPDC_ERR_UNSUPPORTED, "weighted min-sum: rows of at most %d edges (code has %d)", bpdc::kWmsMaxRowDeg,
+                d.max_row_deg);
   if (bpdc::wms_backward_lds(d, K) > (size_t)p->max_lds || bpdc::wms_forward_lds(d) > (size_t)p->max_lds)
     return fail(BPDC_ERR_UNSUPPORTED, "code too large for the weighted min-sum kernels (LDS)");
   return BPDC_OK;
 }
 
 static size_t wms_ckpt_bytes(bpdc_plan p, int32_t code, int64_t B, int32_t K) {
-  const bpdc::DevCode& d = p->codes[code]->dev;
-  const int64_t nck = (p->kp.T1 + K - 1) / K + (p->kp.T2 + K - 1) / K;
-  return (size_t)B * (size_t)nck * (size_t)d.E * sizeof(float);
+  return bpdc::wms_ckpt_bytes(p->codes[code]->dev, p->kp, B, K);
 }
 
 bpdc_status bpdc_wms_ckpt_size(bpdc_plan p, int32_t code, int64_t B, int32_t K, size_t* bytes) {
@@ -1125,7 +1126,7 @@ bpdc_status bpdc_wms_forward(bpdc_plan p, int32_t code, const float* d_w, const 
   if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
     return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
   HIP_TRY(bpdc::wms_forward(p->codes[code]->dev, p->kp, d_w, d_syn, B, shot_offset, K, d_post, d_cut, d_flags,
-                            (float*)d_ckpt, p->num_cu, p->max_lds, (hipStream_t)stream));
+                            d_ckpt, p->num_cu, p->max_lds, (hipStream_t)stream));
   return BPDC_OK;
 }
 
@@ -1140,7 +1141,7 @@ bpdc_status bpdc_wms_backward(bpdc_plan p, int32_t code, const float* d_w, const
   if (!d_ckpt || ckpt_bytes < wms_ckpt_bytes(p, code, B, K))
     return fail(BPDC_ERR_WORKSPACE, "checkpoint buffer of %zu bytes needed", wms_ckpt_bytes(p, code, B, K));
   HIP_TRY(bpdc::wms_backward(p->codes[code]->dev, p->kp, d_w, d_syn, B, K, d_grad_post, d_cut, d_flags,
-                             (const float*)d_ckpt, d_grad_w, p->num_cu, p->max_lds, (hipStream_t)stream));
+                             d_ckpt, d_grad_w, p->num_cu, p->max_lds, (hipStream_t)stream));
   return BPDC_OK;
 }
 

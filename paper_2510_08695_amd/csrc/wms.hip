@@ -1,23 +1,40 @@
 // Weighted min-sum BP+DC with learned per-edge scales, and its adjoint.
 //
 // Forward: the decoder of the other kernels with r_e = sign * (w_e * min of
-// the other |q|) and a separate weight vector per pass (before / after
+// the other |q|) and a separate scale vector per pass (before / after
 // degeneracy cutting), always T iterations per pass (unrolled, no early
-// stop).  The per-edge messages q at iterations 0, K, 2K, ... of each pass
-// are stored as checkpoints.  Backward: for each shot and pass, from the last
-// checkpoint segment to the first, the K iterations of a segment are
-// recomputed from its checkpoint and then run in reverse:
+// stop).  Every K iterations the state of each check is stored as a
+// checkpoint: the smallest and second smallest |q| over its row, their
+// positions, the signs of its q and the parity of those signs with the
+// syndrome bit (12 bytes per check).  That state determines every r of the
+// iteration, so a checkpoint restarts the decoder exactly.
+//
+// Backward: for each shot and pass, from the last checkpoint segment to the
+// first, the check states of the segment's iterations are recomputed from its
+// checkpoint and then walked in reverse:
 //   L_v = prior_v + sum_e r_e,   q_e = sat(L_v - r_e)      (linear, 0 where saturated)
 //   r_e = sigma_e * w_e * |q_e*|  with e* the edge holding the minimum over
 //         the other edges of the check (the second minimum for the argmin
 //         edge), sigma_e the sign (syndrome bit times the other signs, locally
-//         constant):  dr_e/dw_e = sigma_e |q_e*|,  dr_e/dq_e* = sigma_e w_e sgn(q_e*).
-// The cut set is held fixed (it is a function of the first pass, not
-// differentiated), and with the channel prior the second pass depends on the
-// first only through the cut, so each pass's gradient comes from its own
-// posteriors.  One workgroup per shot; messages of a segment live in LDS;
-// per-edge weight gradients are summed in LDS and added to the output once
-// per workgroup.
+//         constant):  dr_e/dw_e = sigma_e |q_e*|,  dr_e/dq_e* = sigma_e w_e sgn(q_e*),
+// so a check passes gradient back to two of its edges only: the argmin (from
+// every other edge) and the second argmin (from the argmin edge).  The cut set
+// is held fixed (a function of the first pass, not differentiated), and with
+// the channel prior the second pass depends on the first only through the
+// cut, so each pass's gradient comes from its own posteriors (a shot without
+// DC reports its first-pass posteriors in both rows, so its first pass takes
+// the gradient of both).
+//
+// Layout: one wave decodes one shot at a time (no workgroup barrier inside
+// the decode: the lanes of a wave step together, and LDS traffic within a
+// wave is ordered by a wavefront fence); a workgroup holds several waves,
+// which share the code's index tables and both scale vectors, staged in LDS
+// once.  Per wave, the messages live in one per-edge array updated in place
+// (the check phase turns a row's q into its r, the variable phase a column's
+// r into its q: every edge belongs to one row and one column).  Lanes own
+// checks c = lane + 64 k in the check phase and columns v = lane + 64 k in
+// the variable phase.  Weight gradients are summed per workgroup in LDS
+// (float atomics) and added to the output once per workgroup.
 #include <algorithm>
 #include <cstdlib>
 
@@ -32,273 +49,498 @@ namespace {
 using bpdc_dev::u32;
 using bpdc_dev::u64;
 
+constexpr u32 kNone = 31u;  // position field of a check state: no such edge
+
+// Device-side view of a code (global memory).
 struct WCode {
-  int n, m, md, E;
-  const int32_t* rp;      // H CSR row pointer
-  const int32_t* col;     // H CSR columns
-  const int32_t* cp;      // CSC column pointer
-  const int32_t* ce;      // CSC -> CSR edge ids (ascending rows)
-  const int32_t* drp;
-  const int32_t* dcol;
-  const float* lam;
+  int n, m, md, E, dnnz;
+  const int32_t* rp;    // H CSR row pointer [m + 1]
+  const int32_t* col;   // H CSR columns [E]
+  const int32_t* cp;    // CSC column pointer [n + 1]
+  const int32_t* ce;    // CSC -> CSR edge ids [E] (ascending rows)
+  const int32_t* erow;  // row of each CSR edge [E]
+  const int32_t* drp;   // D CSR row pointer [md + 1]
+  const int32_t* dcol;  // D CSR columns [dnnz]
+  const float* lam;     // prior LLRs [n]
 };
 
-// Check half of one iteration for all checks: r from q (weights w).
-__device__ void wms_check_phase(const WCode& C, const u32* synw, const float* q, float* r, const float* w,
-                                float lsat) {
-  for (int c = threadIdx.x; c < C.m; c += blockDim.x) {
-    const int e0 = C.rp[c], e1 = C.rp[c + 1];
-    u32 neg = (synw[c >> 5] >> (c & 31)) & 1u;
-    float m1 = lsat, m2 = lsat;
-    int amin = -1;
-    for (int e = e0; e < e1; ++e) {
-      const float a = fabsf(q[e]);
-      neg ^= (q[e] < 0.0f) ? 1u : 0u;
+// The code's tables and the scales of both passes in LDS (shared by the waves
+// of a workgroup).
+struct WTab {
+  int32_t* rp;   // [m + 1]
+  int32_t* cp;   // [n + 1]
+  int32_t* ce;   // [E]
+  int32_t* col;  // [E] (forward: stop test)
+  int32_t* drp;  // [md + 1] (forward: DC)
+  int32_t* dcol; // [dnnz] (forward: DC)
+  float* w;      // [2][E]
+  float* lam;    // [n]
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// Bytes of the shared tables; `forward` adds the stop-test and DC tables.
+__host__ __device__ inline size_t wtab_bytes(int n, int m, int md, int E, int dnnz, bool forward) {
+  size_t b = align16((size_t)(m + 1) * 4) + align16((size_t)(n + 1) * 4) + align16((size_t)E * 4) +
+             align16((size_t)2 * E * 4) + align16((size_t)n * 4);
+  if (forward) b += align16((size_t)E * 4) + align16((size_t)(md + 1) * 4) + align16((size_t)std::max(dnnz, 1) * 4);
+  return b;
+}
+
+__device__ WTab carve_tab(unsigned char* base, const WCode& C, bool forward) {
+  WTab t;
+  unsigned char* p = base;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = p;
+    p += align16(bytes);
+    return q;
+  };
+  t.rp = (int32_t*)take((size_t)(C.m + 1) * 4);
+  t.cp = (int32_t*)take((size_t)(C.n + 1) * 4);
+  t.ce = (int32_t*)take((size_t)C.E * 4);
+  t.w = (float*)take((size_t)2 * C.E * 4);
+  t.lam = (float*)take((size_t)C.n * 4);
+  if (forward) {
+    t.col = (int32_t*)take((size_t)C.E * 4);
+    t.drp = (int32_t*)take((size_t)(C.md + 1) * 4);
+    t.dcol = (int32_t*)take((size_t)std::max(C.dnnz, 1) * 4);
+  } else {
+    t.col = t.drp = t.dcol = nullptr;
+  }
+  return t;
+}
+
+// All threads of the workgroup copy the tables, then one workgroup barrier
+// (before any per-wave work, reached by every thread).
+__device__ void load_tab(const WTab& t, const WCode& C, const float* w, bool forward) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i <= C.m; i += nt) t.rp[i] = C.rp[i];
+  for (int i = tid; i <= C.n; i += nt) t.cp[i] = C.cp[i];
+  for (int k = tid; k < C.E; k += nt) t.ce[k] = C.ce[k];
+  for (int i = tid; i < 2 * C.E; i += nt) t.w[i] = w[i];
+  for (int i = tid; i < C.n; i += nt) t.lam[i] = C.lam[i];
+  if (forward) {
+    for (int i = tid; i < C.E; i += nt) t.col[i] = C.col[i];
+    for (int i = tid; i <= C.md; i += nt) t.drp[i] = C.drp[i];
+    for (int i = tid; i < C.dnnz; i += nt) t.dcol[i] = C.dcol[i];
+  }
+  __syncthreads();
+}
+
+// Order the LDS accesses of one wave (its lanes execute in lockstep; the
+// fences keep the compiler from moving LDS operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// State of one check in one iteration (computed from the q of the previous
+// iteration): |q| minima and the bits
+//   [0, 5) position of the minimum in the row (kNone: every |q| >= lsat),
+//   [5, 10) position of the second minimum (kNone: none below lsat),
+//   [10] parity of the syndrome bit and the q signs, [11, 32) q sign bits.
+struct __align__(16) CState {
+  float m1, m2;
+  u32 bits, pad;
+};
+
+__device__ __forceinline__ u32 cs_a1(u32 bits) { return bits & 31u; }
+__device__ __forceinline__ u32 cs_a2(u32 bits) { return (bits >> 5) & 31u; }
+__device__ __forceinline__ u32 cs_neg(u32 bits) { return (bits >> 10) & 1u; }
+__device__ __forceinline__ u32 cs_qsign(u32 bits, int k) { return (bits >> (11 + k)) & 1u; }
+
+// r of the edge at row position k of a check (scale w): w * (min2 on the
+// argmin edge, min1 elsewhere), negative iff the parity of the syndrome bit
+// and the other signs is odd.
+__device__ __forceinline__ float cs_r(const CState& s, int k, float w) {
+  const float mag = ((u32)k == cs_a1(s.bits)) ? s.m2 : s.m1;
+  const float val = w * mag;
+  return (cs_neg(s.bits) ^ cs_qsign(s.bits, k)) ? -val : val;
+}
+
+// Check state from the q of a row (strict '<' in row order: the first
+// minimum wins; minima start at lsat).  RDM bounds the row degree: the row's
+// loads are issued together.
+template <int RDM>
+__device__ __forceinline__ CState check_state(const float* msg, int e0, int deg, u32 sbit, float lsat) {
+  float q[RDM];
+#pragma unroll
+  for (int k = 0; k < RDM; ++k)
+    if (k < deg) q[k] = msg[e0 + k];
+  float m1 = lsat, m2 = lsat;
+  u32 a1 = kNone, a2 = kNone, neg = sbit, qs = 0u;
+#pragma unroll
+  for (int k = 0; k < RDM; ++k)
+    if (k < deg) {
+      const float a = fabsf(q[k]);
+      const u32 sg = (q[k] < 0.0f) ? 1u : 0u;
+      neg ^= sg;
+      qs |= sg << k;
       if (a < m1) {
         m2 = m1;
+        a2 = a1;
         m1 = a;
-        amin = e;
+        a1 = (u32)k;
       } else if (a < m2) {
         m2 = a;
+        a2 = (u32)k;
       }
     }
-    for (int e = e0; e < e1; ++e) {
-      const float val = w[e] * ((e == amin) ? m2 : m1);
-      r[e] = (neg ^ ((q[e] < 0.0f) ? 1u : 0u)) ? -val : val;
-    }
-  }
+  CState s;
+  s.m1 = m1;
+  s.m2 = m2;
+  s.bits = a1 | (a2 << 5) | (neg << 10) | (qs << 11);
+  s.pad = 0u;
+  return s;
 }
 
-// Variable half: L = prior + sum r (ascending check order), q = sat(L - r).
-__device__ void wms_var_phase(const WCode& C, const u32* cutw, const float* r, float* q, float* L, float lsat) {
-  const float INF = __builtin_huge_valf();
-  for (int v = threadIdx.x; v < C.n; v += blockDim.x) {
-    const int k0 = C.cp[v], k1 = C.cp[v + 1];
-    if ((cutw[v >> 5] >> (v & 31)) & 1u) {
-      for (int k = k0; k < k1; ++k) q[C.ce[k]] = lsat;
-      L[v] = INF;
-      continue;
-    }
-    float Lv = C.lam[v];
-    for (int k = k0; k < k1; ++k) Lv = Lv + r[C.ce[k]];
-    for (int k = k0; k < k1; ++k) {
-      const int e = C.ce[k];
-      q[e] = bpdc_dev::sat(Lv - r[e], lsat);
-    }
-    L[v] = Lv;
-  }
+// The r of every edge of a row from its state, in place of the row's messages.
+template <int RDM>
+__device__ __forceinline__ void write_r(float* msg, const float* wp, int e0, int deg, const CState& st) {
+  float w[RDM];
+#pragma unroll
+  for (int k = 0; k < RDM; ++k)
+    if (k < deg) w[k] = wp[e0 + k];
+#pragma unroll
+  for (int k = 0; k < RDM; ++k)
+    if (k < deg) msg[e0 + k] = cs_r(st, k, w[k]);
 }
 
-__device__ void wms_init_q(const WCode& C, const u32* cutw, float* q, float lsat) {
-  for (int v = threadIdx.x; v < C.n; v += blockDim.x) {
-    const bool cut = (cutw[v >> 5] >> (v & 31)) & 1u;
-    const float q0 = cut ? lsat : bpdc_dev::sat(C.lam[v], lsat);
-    for (int k = C.cp[v]; k < C.cp[v + 1]; ++k) q[C.ce[k]] = q0;
-  }
+struct WArgs {
+  WCode C;
+  const uint64_t* syn;
+  int64_t B;
+  int64_t shot_offset;
+  int K, nck1, nck2;
+  const float* w;          // [2][E]
+  float* post;             // [2][B][n] (forward)
+  uint64_t* cut;           // [B][ceil(n/64)] (forward: out; backward: in)
+  uint8_t* flags;          // [B] (forward: out; backward: in)
+  float* ck_m1;            // checkpoints: three planes [pass-major shot-slot][m] (see ck_index)
+  float* ck_m2;
+  u32* ck_bits;
+  const float* gpost;      // [2][B][n] (backward)
+  float* gw;               // [2][E] (backward, accumulated)
+  size_t wave_bytes;       // per-wave LDS
+  size_t tab_bytes;        // shared LDS (tables; backward: + weight-gradient sums)
+  KParams p;
+};
+
+// Row of checkpoint j of shot b in pass `pass` in the checkpoint planes.
+__device__ __forceinline__ size_t ck_index(const WArgs& a, int pass, int64_t b, int j) {
+  return pass ? ((size_t)a.B * a.nck1 + (size_t)b * a.nck2 + j) : ((size_t)b * a.nck1 + j);
 }
 
-__global__ void __launch_bounds__(256) k_wms_forward(WCode C, const float* w, const uint64_t* syn, int64_t B,
-                                                     int64_t shot_offset, int K, int nck1, int nck2, float* post,
-                                                     uint64_t* cut_out, uint8_t* flags, float* ckpt, KParams P) {
+// DC nomination of one row of D (bpdc_device.h's rule, streamed from the
+// tables): the row maximum of the saturated posteriors, the tie threshold,
+// the number of ties, then the chosen tie in ascending column order.
+__device__ int wms_dc_pick(const int32_t* dcol, int e0, int deg, const float* L, float lsat, float tie_eps,
+                           int tie_lowest, u64 seed, u64 shot, u64 row) {
+  float lmax = bpdc_dev::sat(L[dcol[e0]], lsat);
+  for (int k = 1; k < deg; ++k) lmax = fmaxf(lmax, bpdc_dev::sat(L[dcol[e0 + k]], lsat));
+  const float scale = fmaxf(1.0f, fabsf(lmax));
+  const float thr = lmax - tie_eps * scale;
+  int nt = 0;
+  for (int k = 0; k < deg; ++k) nt += (bpdc_dev::sat(L[dcol[e0 + k]], lsat) >= thr) ? 1 : 0;
+  int want = 0;
+  if (!tie_lowest && nt > 1) want = (int)bpdc_dev::scale_draw(bpdc_dev::tie_hash(seed, shot, row), (u32)nt);
+  int seen = 0;
+  for (int k = 0; k < deg; ++k) {
+    const int c = dcol[e0 + k];
+    if (bpdc_dev::sat(L[c], lsat) >= thr) {
+      if (seen == want) return c;
+      ++seen;
+    }
+  }
+  return dcol[e0];
+}
+
+// CDM, RDM: bounds on the column and row degrees (a column's or row's edge ids
+// and messages stay in registers, and its loads are issued together).
+template <int CDM, int RDM>
+__global__ void __launch_bounds__(512) k_wms_forward(WArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int sUnsat;
+  const WCode& C = a.C;
+  const WTab tb = carve_tab(smem, C, true);
+  load_tab(tb, C, a.w, true);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int n = C.n, m = C.m, E = C.E;
-  float* q = (float*)smem;
-  float* r = q + E;
-  float* L = r + E;
-  u32* cutw = (u32*)(L + n);
-  u32* synw = cutw + ((n + 31) >> 5);
+  const int nwc = (n + 31) >> 5, swc = (m + 31) >> 5;
   const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
-  const float LS = P.lsat, INF = __builtin_huge_valf();
-  const int nck[2] = {nck1, nck2};
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-    for (int i = threadIdx.x; i < ((m + 31) >> 5); i += blockDim.x) {
-      const uint64_t x = syn[b * sw64 + (i >> 1)];
+  unsigned char* mine = smem + a.tab_bytes + (size_t)wave * a.wave_bytes;
+  float* msg = (float*)mine;                              // [E]
+  float* L = msg + E;                                     // [n]
+  u32* cutw = (u32*)(L + n);                              // [nwc]
+  u32* synw = cutw + nwc;                                 // [swc]
+  const float LS = a.p.lsat, INF = __builtin_huge_valf();
+  const int K = a.K;
+
+  for (int64_t b = (int64_t)blockIdx.x * nwaves + wave; b < a.B; b += (int64_t)gridDim.x * nwaves) {
+    for (int i = lane; i < swc; i += 64) {
+      const uint64_t x = a.syn[b * sw64 + (i >> 1)];
       synw[i] = (i & 1) ? (u32)(x >> 32) : (u32)x;
     }
-    for (int i = threadIdx.x; i < ((n + 31) >> 5); i += blockDim.x) cutw[i] = 0u;
-    __syncthreads();
+    for (int i = lane; i < nwc; i += 64) cutw[i] = 0u;
+    wave_sync();
     bool conv = false;
     int pass = 0;
     for (; pass < 2; ++pass) {
-      const int T = pass ? P.T2 : P.T1;
-      const float* wp = w + (size_t)pass * E;
-      float* ck = ckpt + ((size_t)(pass ? B * nck1 : 0) + (size_t)b * nck[pass]) * E;
-      wms_init_q(C, cutw, q, LS);
-      __syncthreads();
-      for (int t = 1; t <= T; ++t) {
-        if ((t - 1) % K == 0)
-          for (int e = threadIdx.x; e < E; e += blockDim.x) ck[(size_t)((t - 1) / K) * E + e] = q[e];
-        wms_check_phase(C, synw, q, r, wp, LS);
-        __syncthreads();
-        wms_var_phase(C, cutw, r, q, L, LS);
-        __syncthreads();
+      const int T = pass ? a.p.T2 : a.p.T1;
+      const float* wp = tb.w + (size_t)pass * E;
+      // first-iteration q: the prior, +lsat on cut columns
+      for (int v = lane; v < n; v += 64) {
+        const bool cv = (cutw[v >> 5] >> (v & 31)) & 1u;
+        const float q0 = cv ? LS : bpdc_dev::sat(tb.lam[v], LS);
+        for (int k = tb.cp[v]; k < tb.cp[v + 1]; ++k) msg[tb.ce[k]] = q0;
       }
-      float* pp = post + ((size_t)pass * B + b) * n;
-      for (int v = threadIdx.x; v < n; v += blockDim.x) pp[v] = (L[v] == INF) ? INF : bpdc_dev::sat(L[v], LS);
-      if (threadIdx.x == 0) sUnsat = 0;
-      __syncthreads();
+      wave_sync();
+      for (int t = 1; t <= T; ++t) {
+        const bool save = ((t - 1) % K) == 0;
+        const int j = (t - 1) / K;
+        // check phase: r of every edge of the row (in place of its q)
+        for (int c = lane; c < m; c += 64) {
+          const int e0 = tb.rp[c], deg = tb.rp[c + 1] - e0;
+          const CState s = check_state<RDM>(msg, e0, deg, (synw[c >> 5] >> (c & 31)) & 1u, LS);
+          if (save) {
+            const size_t row = ck_index(a, pass, b, j) * (size_t)m + c;
+            a.ck_m1[row] = s.m1;
+            a.ck_m2[row] = s.m2;
+            a.ck_bits[row] = s.bits;
+          }
+          write_r<RDM>(msg, wp, e0, deg, s);
+        }
+        wave_sync();
+        // variable phase: L = prior + sum r (ascending rows), q = sat(L - r)
+        for (int v = lane; v < n; v += 64) {
+          const int k0 = tb.cp[v], deg = tb.cp[v + 1] - k0;
+          const bool cv = (cutw[v >> 5] >> (v & 31)) & 1u;
+          int ee[CDM];
+          float rr[CDM];
+#pragma unroll
+          for (int j = 0; j < CDM; ++j)
+            if (j < deg) {
+              ee[j] = tb.ce[k0 + j];
+              rr[j] = msg[ee[j]];
+            }
+          float Lv = tb.lam[v];
+#pragma unroll
+          for (int j = 0; j < CDM; ++j)
+            if (j < deg) Lv = Lv + rr[j];
+#pragma unroll
+          for (int j = 0; j < CDM; ++j)
+            if (j < deg) msg[ee[j]] = cv ? LS : bpdc_dev::sat(Lv - rr[j], LS);
+          L[v] = cv ? INF : Lv;
+        }
+        wave_sync();
+      }
+      float* pp = a.post + ((size_t)pass * a.B + b) * n;
+      for (int v = lane; v < n; v += 64) pp[v] = (L[v] == INF) ? INF : bpdc_dev::sat(L[v], LS);
+      // stop test H e = s with e = [L <= 0]
       int bad = 0;
-      for (int c = threadIdx.x; c < m; c += blockDim.x) {
+      for (int c = lane; c < m; c += 64) {
         u32 par = (synw[c >> 5] >> (c & 31)) & 1u;
-        for (int e = C.rp[c]; e < C.rp[c + 1]; ++e) par ^= (L[C.col[e]] <= 0.0f) ? 1u : 0u;
+        for (int e = tb.rp[c]; e < tb.rp[c + 1]; ++e) par ^= (L[tb.col[e]] <= 0.0f) ? 1u : 0u;
         bad |= (int)par;
       }
-      if (bad) atomicOr(&sUnsat, 1);
-      __syncthreads();
-      conv = sUnsat == 0;
+      conv = __ballot(bad) == 0ull;
       if (pass == 1 || conv) break;
       // degeneracy cutting on the first-pass posteriors
-      for (int h = threadIdx.x; h < C.md; h += blockDim.x) {
-        const int e0 = C.drp[h], deg = C.drp[h + 1] - e0;
+      for (int h = lane; h < C.md; h += 64) {
+        const int e0 = tb.drp[h], deg = tb.drp[h + 1] - e0;
         if (deg == 0) continue;
-        int cols[32];
-        float vals[32];
-        for (int k = 0; k < deg; ++k) {
-          cols[k] = C.dcol[e0 + k];
-          vals[k] = bpdc_dev::sat(L[cols[k]], LS);
-        }
-        const int pick = bpdc_dev::dc_pick<32>(cols, vals, deg, P.tie_eps, P.tie_lowest, P.seed,
-                                               (u64)(shot_offset + b), (u64)h);
+        const int pick = wms_dc_pick(tb.dcol, e0, deg, L, LS, a.p.tie_eps, a.p.tie_lowest, a.p.seed,
+                                     (u64)(a.shot_offset + b), (u64)h);
         atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
       }
-      __syncthreads();
+      wave_sync();
     }
     const bool dc = pass == 1;
     if (!dc) {  // second-pass rows of shots without DC are copies of the first pass
-      float* p0 = post + (size_t)b * n;
-      float* p1 = post + ((size_t)B + b) * n;
-      for (int v = threadIdx.x; v < n; v += blockDim.x) p1[v] = p0[v];
+      const float* p0 = a.post + (size_t)b * n;
+      float* p1 = a.post + ((size_t)a.B + b) * n;
+      for (int v = lane; v < n; v += 64) p1[v] = p0[v];
     }
-    for (int i = threadIdx.x; i < nw64; i += blockDim.x) {
+    for (int i = lane; i < nw64; i += 64) {
       const u32 lo = cutw[2 * i];
-      const u32 hi = (2 * i + 1 < ((n + 31) >> 5)) ? cutw[2 * i + 1] : 0u;
-      cut_out[b * nw64 + i] = dc ? (((u64)hi << 32) | lo) : 0ull;
+      const u32 hi = (2 * i + 1 < nwc) ? cutw[2 * i + 1] : 0u;
+      a.cut[b * nw64 + i] = dc ? (((u64)hi << 32) | lo) : 0ull;
     }
-    if (threadIdx.x == 0) flags[b] = (uint8_t)((conv ? 1 : 0) | (dc ? 2 : 0));
-    __syncthreads();
+    if (lane == 0) a.flags[b] = (uint8_t)((conv ? 1 : 0) | (dc ? 2 : 0));
+    wave_sync();
   }
 }
 
-__device__ __forceinline__ float sgnf(float x) { return (x > 0.0f) ? 1.0f : ((x < 0.0f) ? -1.0f : 0.0f); }
+__device__ __forceinline__ float sgn_of(float mag, u32 sign) {
+  // sign of a q from its magnitude (a minimum over the row) and sign bit: 0 at q = 0
+  return mag == 0.0f ? 0.0f : (sign ? -1.0f : 1.0f);
+}
 
-__global__ void __launch_bounds__(256) k_wms_backward(WCode C, const float* w, const uint64_t* syn, int64_t B,
-                                                      int K, int nck1, int nck2, const float* gpost,
-                                                      const uint64_t* cut_in, const uint8_t* flags,
-                                                      const float* ckpt, float* gw_out, KParams P) {
+template <int CDM, int RDM>
+__global__ void __launch_bounds__(512) k_wms_backward(WArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const WCode& C = a.C;
+  const WTab tb = carve_tab(smem, C, false);
   const int n = C.n, m = C.m, E = C.E;
-  float* qs = (float*)smem;          // [(K + 1) * E] messages q(t0 .. t0 + K)
-  float* r = qs + (size_t)(K + 1) * E;  // [E] r(t) (recomputed)
-  float* gq = r + E;                 // [E] dLoss/dq(t)
-  float* gqn = gq + E;               // [E] dLoss/dq(t - 1) being accumulated (the two swap roles)
-  float* gr = gqn + E;               // [E] dLoss/dr(t)
-  float* gw = gr + E;                // [2 * E] per-workgroup weight gradients
-  float* L = gw + 2 * E;             // [n]
-  u32* cutw = (u32*)(L + n);
-  u32* synw = cutw + ((n + 31) >> 5);
+  float* gws = (float*)(smem + wtab_bytes(n, m, C.md, E, C.dnnz, false));  // [2][E] weight-gradient sums
+  for (int i = threadIdx.x; i < 2 * E; i += blockDim.x) gws[i] = 0.0f;
+  load_tab(tb, C, a.w, false);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int nwc = (n + 31) >> 5, swc = (m + 31) >> 5;
   const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
-  const float LS = P.lsat;
-  const int nck[2] = {nck1, nck2};
-  for (int e = threadIdx.x; e < 2 * E; e += blockDim.x) gw[e] = 0.0f;
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-    for (int i = threadIdx.x; i < ((m + 31) >> 5); i += blockDim.x) {
-      const uint64_t x = syn[b * sw64 + (i >> 1)];
+  const int K = a.K;
+  unsigned char* mine = smem + a.tab_bytes + (size_t)wave * a.wave_bytes;
+  // check states of the segment's iterations, [K][m] planes; only the lane that
+  // owns a row reads or writes its entries
+  float* cm1 = (float*)mine;
+  float* cm2 = cm1 + (size_t)K * m;
+  u32* cbits = (u32*)(cm2 + (size_t)K * m);
+  float* msg = (float*)(cbits + (size_t)K * m);            // [E] messages: q or r (in place)
+  float* grad = msg + E;                                   // [E] dLoss/dq, then dLoss/dr, in place
+  u32* cutw = (u32*)(grad + E);                            // [nwc]
+  u32* synw = cutw + nwc;                                  // [swc]
+  const float LS = a.p.lsat;
+  auto cs_at = [&](int j, int c) {
+    CState st;
+    const size_t i = (size_t)j * m + c;
+    st.m1 = cm1[i];
+    st.m2 = cm2[i];
+    st.bits = cbits[i];
+    st.pad = 0u;
+    return st;
+  };
+
+  for (int64_t b = (int64_t)blockIdx.x * nwaves + wave; b < a.B; b += (int64_t)gridDim.x * nwaves) {
+    for (int i = lane; i < swc; i += 64) {
+      const uint64_t x = a.syn[b * sw64 + (i >> 1)];
       synw[i] = (i & 1) ? (u32)(x >> 32) : (u32)x;
     }
-    const bool dc = (flags[b] & 2) != 0;
+    const bool dc = (a.flags[b] & 2) != 0;
     for (int pass = dc ? 1 : 0; pass >= 0; --pass) {
-      for (int i = threadIdx.x; i < ((n + 31) >> 5); i += blockDim.x) {
-        const uint64_t x = cut_in[b * nw64 + (i >> 1)];
+      for (int i = lane; i < nwc; i += 64) {
+        const uint64_t x = a.cut[b * nw64 + (i >> 1)];
         cutw[i] = pass == 0 ? 0u : ((i & 1) ? (u32)(x >> 32) : (u32)x);
       }
-      for (int e = threadIdx.x; e < E; e += blockDim.x) gq[e] = 0.0f;
-      __syncthreads();
-      const int T = pass ? P.T2 : P.T1;
-      const float* wp = w + (size_t)pass * E;
-      const float* ck = ckpt + ((size_t)(pass ? B * nck1 : 0) + (size_t)b * nck[pass]) * E;
-      const float* gp = gpost + ((size_t)pass * B + b) * n;
-      // a shot without DC reports its first-pass posteriors in both output rows,
-      // so pass 0 collects the gradient of both rows
-      const float* gp2 = dc ? nullptr : gpost + ((size_t)B + b) * n;
-      for (int s = nck[pass] - 1; s >= 0; --s) {
-        const int t0 = s * K, t1 = min(T, t0 + K);
-        for (int e = threadIdx.x; e < E; e += blockDim.x) qs[e] = ck[(size_t)s * E + e];
-        __syncthreads();
-        for (int t = t0 + 1; t <= t1; ++t) {  // recompute the segment's messages
-          wms_check_phase(C, synw, qs + (size_t)(t - t0 - 1) * E, r, wp, LS);
-          __syncthreads();
-          wms_var_phase(C, cutw, r, qs + (size_t)(t - t0) * E, L, LS);
-          __syncthreads();
+      for (int e = lane; e < E; e += 64) grad[e] = 0.0f;
+      const int T = pass ? a.p.T2 : a.p.T1;
+      const int nck = pass ? a.nck2 : a.nck1;
+      const float* wp = tb.w + (size_t)pass * E;
+      float* gwp = gws + (size_t)pass * E;
+      const float* gp = a.gpost + ((size_t)pass * a.B + b) * n;
+      const float* gp2 = dc ? nullptr : a.gpost + ((size_t)a.B + b) * n;
+      for (int s = nck - 1; s >= 0; --s) {
+        const int t0 = s * K, len = min(T, t0 + K) - t0;
+        // the checkpoint (state of iteration t0 + 1) and its r
+        for (int c = lane; c < m; c += 64) {
+          const size_t row = ck_index(a, pass, b, s) * (size_t)m + c;
+          CState st;
+          st.m1 = cm1[c] = a.ck_m1[row];
+          st.m2 = cm2[c] = a.ck_m2[row];
+          st.bits = cbits[c] = a.ck_bits[row];
+          const int e0 = tb.rp[c];
+          write_r<RDM>(msg, wp, e0, tb.rp[c + 1] - e0, st);
         }
-        for (int t = t1; t > t0; --t) {
-          const float* qp = qs + (size_t)(t - t0 - 1) * E;  // q(t - 1)
-          wms_check_phase(C, synw, qp, r, wp, LS);          // r(t)
-          __syncthreads();
-          // variable side: L(t) = prior + sum r(t); q(t) = sat(L - r)
-          for (int v = threadIdx.x; v < n; v += blockDim.x) {
-            const int k0 = C.cp[v], k1 = C.cp[v + 1];
-            if ((cutw[v >> 5] >> (v & 31)) & 1u) {
-              for (int k = k0; k < k1; ++k) gr[C.ce[k]] = 0.0f;
-              continue;
-            }
-            float Lv = C.lam[v];
-            for (int k = k0; k < k1; ++k) Lv = Lv + r[C.ce[k]];
-            float gL = (t == T && fabsf(Lv) < LS) ? (gp2 ? gp[v] + gp2[v] : gp[v]) : 0.0f;
-            for (int k = k0; k < k1; ++k) {
-              const int e = C.ce[k];
-              if (fabsf(Lv - r[e]) < LS) gL += gq[e];
-            }
-            for (int k = k0; k < k1; ++k) {
-              const int e = C.ce[k];
-              gr[e] = (fabsf(Lv - r[e]) < LS) ? gL - gq[e] : gL;
-            }
-          }
-          for (int e = threadIdx.x; e < E; e += blockDim.x) gqn[e] = 0.0f;
-          __syncthreads();
-          // check side: through w * min |q| and the (locally constant) signs
-          for (int c = threadIdx.x; c < m; c += blockDim.x) {
-            const int e0 = C.rp[c], e1 = C.rp[c + 1];
-            float m1 = LS, m2 = LS;
-            int a1 = -1, a2 = -1;
-            u32 neg = (synw[c >> 5] >> (c & 31)) & 1u;
-            for (int e = e0; e < e1; ++e) {
-              neg ^= (qp[e] < 0.0f) ? 1u : 0u;
-              const float a = fabsf(qp[e]);
-              if (a < m1) {
-                m2 = m1;
-                a2 = a1;
-                m1 = a;
-                a1 = e;
-              } else if (a < m2) {
-                m2 = a;
-                a2 = e;
+        wave_sync();
+        // recompute the forward through the segment: states of iterations t0 + 2 .. t0 + len
+        for (int j = 1; j < len; ++j) {
+          for (int v = lane; v < n; v += 64) {
+            const int k0 = tb.cp[v], deg = tb.cp[v + 1] - k0;
+            const bool cv = (cutw[v >> 5] >> (v & 31)) & 1u;
+            int ee[CDM];
+            float rr[CDM];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) {
+                ee[i] = tb.ce[k0 + i];
+                rr[i] = msg[ee[i]];
               }
-            }
+            float Lv = tb.lam[v];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) Lv = Lv + rr[i];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) msg[ee[i]] = cv ? LS : bpdc_dev::sat(Lv - rr[i], LS);
+          }
+          wave_sync();
+          for (int c = lane; c < m; c += 64) {
+            const int e0 = tb.rp[c], deg = tb.rp[c + 1] - e0;
+            const CState st = check_state<RDM>(msg, e0, deg, (synw[c >> 5] >> (c & 31)) & 1u, LS);
+            const size_t i = (size_t)j * m + c;
+            cm1[i] = st.m1;
+            cm2[i] = st.m2;
+            cbits[i] = st.bits;
+            write_r<RDM>(msg, wp, e0, deg, st);
+          }
+          wave_sync();
+        }
+        // reverse sweep over the segment; msg holds the r of the iteration at hand
+        for (int j = len - 1; j >= 0; --j) {
+          const int t = t0 + j + 1;
+          // variable side: dLoss/dr from dLoss/dq (and dLoss/dpost at the last iteration)
+          for (int v = lane; v < n; v += 64) {
+            const int k0 = tb.cp[v], deg = tb.cp[v + 1] - k0;
+            const bool cv = (cutw[v >> 5] >> (v & 31)) & 1u;
+            int ee[CDM];
+            float rr[CDM], gq[CDM];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) {
+                ee[i] = tb.ce[k0 + i];
+                rr[i] = msg[ee[i]];
+                gq[i] = grad[ee[i]];
+              }
+            float Lv = tb.lam[v];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) Lv = Lv + rr[i];
+            float gL = 0.0f;
+            if (t == T && fabsf(Lv) < LS) gL = gp2 ? gp[v] + gp2[v] : gp[v];
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg && fabsf(Lv - rr[i]) < LS) gL += gq[i];
+            // a cut column's messages are constants: no gradient through its edges
+#pragma unroll
+            for (int i = 0; i < CDM; ++i)
+              if (i < deg) grad[ee[i]] = cv ? 0.0f : ((fabsf(Lv - rr[i]) < LS) ? gL - gq[i] : gL);
+          }
+          wave_sync();
+          // check side: dLoss/dw and dLoss/dq of the previous iteration (argmin and
+          // second argmin of each row only); then the r of the previous iteration
+          for (int c = lane; c < m; c += 64) {
+            const CState sc = cs_at(j, c);
+            const int e0 = tb.rp[c], e1 = tb.rp[c + 1];
+            const u32 a1 = cs_a1(sc.bits), a2 = cs_a2(sc.bits);
+            float g1 = 0.0f, g2 = 0.0f;  // into the argmin's q, into the second argmin's q
             for (int e = e0; e < e1; ++e) {
-              const float g = gr[e];
+              const int k = e - e0;
+              const float g = grad[e];
+              grad[e] = 0.0f;
               if (g == 0.0f) continue;
-              const float mag = (e == a1) ? m2 : m1;
-              const int src = (e == a1) ? a2 : a1;
-              const float sig = (neg ^ ((qp[e] < 0.0f) ? 1u : 0u)) ? -1.0f : 1.0f;
-              // edge e belongs to this thread's check only: a plain add
-              gw[(size_t)pass * E + e] += g * sig * mag;
-              if (src >= 0) gqn[src] += g * sig * wp[e] * sgnf(qp[src]);
+              const bool isa1 = (u32)k == a1;
+              const float mag = isa1 ? sc.m2 : sc.m1;
+              const float sg = (cs_neg(sc.bits) ^ cs_qsign(sc.bits, k)) ? -g : g;
+              atomicAdd(&gwp[e], sg * mag);
+              if (isa1) g2 += sg * wp[e];
+              else g1 += sg * wp[e];
+            }
+            if (a1 != kNone) {
+              grad[e0 + a1] = g1 * sgn_of(sc.m1, cs_qsign(sc.bits, a1));
+              if (a2 != kNone) grad[e0 + a2] = g2 * sgn_of(sc.m2, cs_qsign(sc.bits, a2));
+            }
+            if (j > 0) {
+              const CState sp = cs_at(j - 1, c);
+              for (int e = e0; e < e1; ++e) msg[e] = cs_r(sp, e - e0, wp[e]);
             }
           }
-          __syncthreads();
-          // dLoss/dq(t - 1) becomes the next step's dLoss/dq(t); the old buffer
-          // is cleared before it accumulates again
-          float* tmp = gq;
-          gq = gqn;
-          gqn = tmp;
+          wave_sync();
         }
       }
     }
   }
-  __syncthreads();
+  __syncthreads();  // every wave has left its shot loop
   for (int e = threadIdx.x; e < 2 * E; e += blockDim.x)
-    if (gw[e] != 0.0f) atomicAdd(&gw_out[e], gw[e]);
+    if (gws[e] != 0.0f) atomicAdd(&a.gw[e], gws[e]);
 }
 
 WCode wcode(const DevCode& d) {
@@ -307,77 +549,131 @@ WCode wcode(const DevCode& d) {
   c.m = d.m;
   c.md = d.md;
   c.E = d.E;
+  c.dnnz = d.dnnz;
   c.rp = d.h_row_ptr;
   c.col = d.h_col;
   c.cp = d.h_col_ptr;
   c.ce = d.h_col_edge;
+  c.erow = d.h_edge_row;
   c.drp = d.d_row_ptr;
   c.dcol = d.d_col;
   c.lam = d.lam;
   return c;
 }
 
-}  // namespace
-
-size_t wms_forward_lds(const DevCode& d) {
-  return (size_t)(2 * d.E + d.n) * 4 + (size_t)(((d.n + 31) / 32) + ((d.m + 31) / 32)) * 4 + 16;
+size_t fwd_wave_bytes(const DevCode& d) {
+  return align16((size_t)(d.E + d.n) * 4 + (size_t)(((d.n + 31) / 32) + ((d.m + 31) / 32)) * 4);
 }
 
-size_t wms_backward_lds(const DevCode& d, int K) {
-  return (size_t)((K + 1) * d.E + 4 * d.E + 2 * d.E + d.n) * 4 + (size_t)(((d.n + 31) / 32) + ((d.m + 31) / 32)) * 4 +
-         16;
+size_t bwd_wave_bytes(const DevCode& d, int K) {
+  return align16((size_t)3 * K * d.m * 4 + (size_t)2 * d.E * 4 + (size_t)(((d.n + 31) / 32) + ((d.m + 31) / 32)) * 4);
 }
 
-// Threads per workgroup of the weighted kernels (one workgroup per shot; 64,
-// 128 or 256): the forward kernel's small LDS footprint lets one-wave
-// workgroups fill the compute units (64, measured fastest on BB144); the
-// adjoint keeps K + 1 message vectors per shot and is LDS-bound, so it takes
-// two waves per shot (128).  BPDC_WMS_THREADS_FWD / _BWD override.
-int wms_threads(bool backward) {
-  const char* e = getenv(backward ? "BPDC_WMS_THREADS_BWD" : "BPDC_WMS_THREADS_FWD");
-  const int v = e ? atoi(e) : (backward ? 128 : 64);
-  return v <= 64 ? 64 : (v <= 128 ? 128 : 256);
+size_t fwd_tab_bytes(const DevCode& d) { return wtab_bytes(d.n, d.m, d.md, d.E, d.dnnz, true); }
+size_t bwd_tab_bytes(const DevCode& d) { return wtab_bytes(d.n, d.m, d.md, d.E, d.dnnz, false) + align16((size_t)2 * d.E * 4); }
+
+// Waves per workgroup of the weighted kernels (each wave decodes its own
+// shots; the workgroup shares one copy of the tables): 8, or fewer when the
+// LDS of one workgroup cannot hold them (on BB144, 8 waves measured 1.3x
+// faster than 4 for the forward and 1.15x for the adjoint, though fewer waves
+// stay resident).  BPDC_WMS_WAVES overrides.
+int wms_waves(size_t tab, size_t per_wave, int max_lds) {
+  const char* e = getenv("BPDC_WMS_WAVES");
+  int w = e ? std::max(1, std::min(8, atoi(e))) : 8;
+  while (w > 1 && tab + (size_t)w * per_wave > (size_t)max_lds) --w;
+  return w;
 }
 
-// Persistent grid: as many workgroups as fit on the device at once, at most B.
+// Persistent grid: as many workgroups as fit on the device at once, at most
+// enough for one shot per wave.
 int wms_grid(const void* kernel, int threads, size_t lds, int num_cu, int64_t B) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) {
     (void)hipGetLastError();
     nb = 1;
   }
-  return (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)nb * num_cu));
+  const int64_t waves = threads / 64;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((B + waves - 1) / waves, (int64_t)nb * num_cu));
 }
 
+WArgs wargs(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K, void* ckpt) {
+  WArgs a;
+  a.C = wcode(d);
+  a.syn = syn;
+  a.B = B;
+  a.shot_offset = 0;
+  a.K = K;
+  a.nck1 = (p.T1 + K - 1) / K;
+  a.nck2 = (p.T2 + K - 1) / K;
+  a.w = w;
+  a.post = nullptr;
+  a.cut = nullptr;
+  a.flags = nullptr;
+  // three planes of (B nck1 + B nck2) m entries each
+  const size_t rows = ((size_t)B * a.nck1 + (size_t)B * a.nck2) * (size_t)d.m;
+  a.ck_m1 = (float*)ckpt;
+  a.ck_m2 = a.ck_m1 + rows;
+  a.ck_bits = (u32*)(a.ck_m2 + rows);
+  a.gpost = nullptr;
+  a.gw = nullptr;
+  a.p = p;
+  return a;
+}
+
+}  // namespace
+
+size_t wms_ckpt_bytes(const DevCode& d, const KParams& p, int64_t B, int K) {
+  const int64_t nck = (p.T1 + K - 1) / K + (p.T2 + K - 1) / K;
+  return (size_t)B * (size_t)nck * (size_t)d.m * 12;
+}
+
+size_t wms_forward_lds(const DevCode& d) { return fwd_tab_bytes(d) + fwd_wave_bytes(d); }
+
+size_t wms_backward_lds(const DevCode& d, int K) { return bwd_tab_bytes(d) + bwd_wave_bytes(d, K); }
+
 hipError_t wms_forward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B,
-                       int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, float* ckpt,
+                       int64_t shot_offset, int K, float* post, uint64_t* cut, uint8_t* flags, void* ckpt,
                        int num_cu, int max_lds, hipStream_t stream) {
-  const size_t lds = wms_forward_lds(d);
-  if (lds > 65536 &&
-      hipFuncSetAttribute((const void*)k_wms_forward, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
+  WArgs a = wargs(d, p, w, syn, B, K, ckpt);
+  a.shot_offset = shot_offset;
+  a.post = post;
+  a.cut = cut;
+  a.flags = flags;
+  a.tab_bytes = fwd_tab_bytes(d);
+  a.wave_bytes = fwd_wave_bytes(d);
+  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8;
+  const void* kern = small ? (const void*)k_wms_forward<4, 8> : (const void*)k_wms_forward<16, kWmsMaxRowDeg>;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
+  const int waves = wms_waves(a.tab_bytes, a.wave_bytes, max_lds);
+  const size_t lds = a.tab_bytes + (size_t)waves * a.wave_bytes;
   (void)hipGetLastError();
-  const int threads = wms_threads(false);
-  const int grid = wms_grid((const void*)k_wms_forward, threads, lds, num_cu, B);
-  const int nck1 = (p.T1 + K - 1) / K, nck2 = (p.T2 + K - 1) / K;
-  hipLaunchKernelGGL(k_wms_forward, dim3(grid), dim3(threads), lds, stream, wcode(d), w, syn, B, shot_offset, K, nck1,
-                     nck2, post, cut, flags, ckpt, p);
+  const int grid = wms_grid(kern, 64 * waves, lds, num_cu, B);
+  if (small) hipLaunchKernelGGL((k_wms_forward<4, 8>), dim3(grid), dim3(64 * waves), lds, stream, a);
+  else hipLaunchKernelGGL((k_wms_forward<16, kWmsMaxRowDeg>), dim3(grid), dim3(64 * waves), lds, stream, a);
   return hipGetLastError();
 }
 
 hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K,
-                        const float* gpost, const uint64_t* cut, const uint8_t* flags, const float* ckpt, float* gw,
+                        const float* gpost, const uint64_t* cut, const uint8_t* flags, const void* ckpt, float* gw,
                         int num_cu, int max_lds, hipStream_t stream) {
-  const size_t lds = wms_backward_lds(d, K);
-  if (lds > 65536 &&
-      hipFuncSetAttribute((const void*)k_wms_backward, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
+  WArgs a = wargs(d, p, w, syn, B, K, const_cast<void*>(ckpt));
+  a.cut = const_cast<uint64_t*>(cut);
+  a.flags = const_cast<uint8_t*>(flags);
+  a.gpost = gpost;
+  a.gw = gw;
+  a.tab_bytes = bwd_tab_bytes(d);
+  a.wave_bytes = bwd_wave_bytes(d, K);
+  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8;
+  const void* kern = small ? (const void*)k_wms_backward<4, 8> : (const void*)k_wms_backward<16, kWmsMaxRowDeg>;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
+  const int waves = wms_waves(a.tab_bytes, a.wave_bytes, max_lds);
+  const size_t lds = a.tab_bytes + (size_t)waves * a.wave_bytes;
   (void)hipGetLastError();
-  const int threads = wms_threads(true);
-  const int grid = wms_grid((const void*)k_wms_backward, threads, lds, num_cu, B);
-  const int nck1 = (p.T1 + K - 1) / K, nck2 = (p.T2 + K - 1) / K;
-  hipLaunchKernelGGL(k_wms_backward, dim3(grid), dim3(threads), lds, stream, wcode(d), w, syn, B, K, nck1, nck2, gpost,
-                     cut, flags, ckpt, gw, p);
+  const int grid = wms_grid(kern, 64 * waves, lds, num_cu, B);
+  if (small) hipLaunchKernelGGL((k_wms_backward<4, 8>), dim3(grid), dim3(64 * waves), lds, stream, a);
+  else hipLaunchKernelGGL((k_wms_backward<16, kWmsMaxRowDeg>), dim3(grid), dim3(64 * waves), lds, stream, a);
   return hipGetLastError();
 }
 
