@@ -219,7 +219,10 @@ bpdc_status bpdc_graph_launch(bpdc_plan plan, void* stream);
 /* Weighted min-sum (learned per-edge scales, one set per pass): the forward
  * runs T1 iterations, DC on shots whose first pass failed, then T2 iterations,
  * with no early stop, and stores check-state checkpoints every `ckpt_every`
- * iterations for the backward.
+ * iterations for the backward (12 bytes per check: both minima of |q| over
+ * the row, their positions, the q signs and their parity with the syndrome
+ * bit).  Rows of H of at most 21 edges, channel second-pass prior, min-sum,
+ * no soft DC (BPDC_ERR_UNSUPPORTED otherwise).
  *   d_w      [2][E] float scales in CSR edge order of H (pass 1, pass 2)
  *   d_post   [2][B][n] float posteriors at the end of each pass (pass-2 rows
  *            of shots without DC are copies of pass 1)
