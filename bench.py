@@ -74,6 +74,28 @@ def committed_traffic(workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def oracle_params(prm, second_pass: str):
+    """Oracle parameters equal to library parameters `prm` (for the cpu_baseline leg)."""
+    import oracle
+    return oracle.OracleParams(max_iter1=prm.max_iter[0], max_iter2=prm.max_iter[1], alpha=prm.alpha,
+                               second_pass_prior=second_pass, stop_on_converge=prm.stop_on_converge,
+                               llr_sat=prm.llr_sat, tie_eps=prm.tie_eps,
+                               tie_break="lowest" if prm.tie_break == 1 else "hash", seed=prm.seed,
+                               rule=prm.rule, soft_period=prm.soft_period,
+                               soft_shift=float(np.float32(prm.soft_shift)))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def wilson(k: int, n: int, z: float = 1.96):
     if n == 0:
         return (0.0, 0.0)
@@ -96,6 +118,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-diag", action="store_true", help="skip the untimed DC-diagnostics pass")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the p sweep of the headline code")
+    ap.add_argument("--sweep-cpu-seconds", type=float, default=3.0)
     ap.add_argument("--workload", default="bb144",
                     choices=["bb144", "toric6", "phen", "hgp64", "wms", "surface7", "circuit", "soft", "toric6ps"],
                     help="bb144: the headline configuration (default); the others are the "
@@ -129,6 +153,7 @@ def main():
                    stop_on_converge=True, llr_sat=64.0, tie_eps=1e-3, tie_break=P.TIE_HASH, seed=1)
     c = P.Code.from_problem(code)
     plan = P.Plan([c], prm, kernel=P.KERNEL_LANE)
+    tuner = plan.describe(0)
     syn = torch.from_numpy(synth.pack_bits(shots.syndromes).view(np.int64)).cuda()
     out = {"corr": torch.empty((B, 3), dtype=torch.int64, device="cuda"),
            "flags": torch.empty(B, dtype=torch.uint8, device="cuda")}
@@ -185,8 +210,11 @@ def main():
                                                                                       8 * ((code.n + 63) // 64) + 1),
                           "launch_ms": launch_ms, "ops_per_launch": ops_per_step}
 
+    result["autotune"] = tuner
     if not args.no_diag:
         result["dc_diagnostics"] = _dc_diagnostics(plan, syn, code.n, 3, stream)
+    if not args.no_sweep:
+        result["p_sweep"] = _p_sweep(args, B, prm, stream)
 
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -218,8 +246,6 @@ def main():
 
     if not args.no_cpu:
         import oracle
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from gpu_helpers import oracle_params
         cores = len(os.sched_getaffinity(0))
         op = oracle_params(prm, "channel")
         done, el, fails = 0, 0.0, 0
@@ -234,6 +260,7 @@ def main():
             fails += int(f.sum())
             done = hi_
         result["cpu_baseline"] = {"value": done / el, "unit": "shots/s", "cores": cores, "kind": "oracle",
+                                  "cpu_model": cpu_model(),
                                   "sample": f"first {done} shots of the same batch, float64 oracle, "
                                             f"{cores} OpenMP threads",
                                   "ler_on_sample": fails / done,
@@ -243,6 +270,42 @@ def main():
 
 # ---------------------------------------------------------------------------------------------
 # secondary configurations (each prints one JSON line)
+
+
+def _p_sweep(args, B, prm, stream):
+    """The headline code at the other error rates of its configuration (p = 0.02, 0.04, 0.06,
+    0.08; 1e6 shots each, seed 2000 + 100 p, one launch per step, the same decoder settings):
+    throughput, roofline fraction, LER, and the float64 oracle on a bounded sample."""
+    import torch
+    import oracle
+    import paper_2510_08695_amd as P
+    import synth
+    out = {}
+    for p in (0.02, 0.04, 0.06, 0.08):
+        code = synth.bb_code("bb144", p=p)
+        shots = synth.make_shots(code, B, 2000 + round(100 * p))
+        plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
+        syn = torch.from_numpy(synth.pack_bits(shots.syndromes).view(np.int64)).cuda()
+        o = plan.decode(syn, want_iters=True)
+        torch.cuda.synchronize()
+        ms = _timed(lambda: plan.decode(syn, out=o), max(3, args.steps // 4), stream)
+        it = o["iters"].cpu().numpy().astype(np.int64)
+        fl = o["flags"].cpu().numpy()
+        n_dc = int(((fl & 2) != 0).sum())
+        ops = OPS_PER_EDGE_ITER * code.H.nnz * int(it.sum()) + OPS_PER_DC_ENTRY * code.D.nnz * n_dc
+        ler, ci = _ler(code, shots.errors, o["corr"].cpu().numpy().view(np.uint64), fl)
+        r = {"shots_per_s": B / (ms / 1e3), "ms_per_step": ms, "ler": ler, "ler_ci95": ci, "dc_rate": n_dc / B,
+             "mean_iters": float(it.sum()) / B, "roofline_frac": ops / (ms / 1e3) / PEAK_LANE_OPS}
+        if not args.no_cpu:
+            cb = _oracle_sample(code, shots.syndromes, shots.errors, oracle_params(prm, "channel"),
+                                args.sweep_cpu_seconds, chunk=20000)
+            k = cb.pop("shots")
+            cb["gpu_ler_on_sample"] = _ler(code, shots.errors[:k], o["corr"].cpu().numpy().view(np.uint64)[:k],
+                                           fl[:k])[0]
+            r["cpu_baseline"] = cb
+        out[str(p)] = r
+        del plan, syn, o, shots
+    return out
 
 
 def _timed(fn, steps, stream):
@@ -310,7 +373,7 @@ def _oracle_sample(code, syndromes, errors, op, seconds, chunk=2000):
             f |= synth.residual_is_logical(errors[done:hi] ^ o["ehat"], code.O)
         fails += int(f.sum())
         done = hi
-    return {"value": done / el, "unit": "shots/s", "cores": cores, "kind": "oracle",
+    return {"value": done / el, "unit": "shots/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {done} shots, float64 oracle, {cores} OpenMP threads", "ler_on_sample": fails / done,
             "shots": done}
 
@@ -331,8 +394,6 @@ def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None
     import torch
     import paper_2510_08695_amd as P
     import synth
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_helpers import oracle_params
     shots = synth.make_shots(code, B, seed)
     c = P.Code.from_problem(code)
     plan = P.Plan([c], prm, kernel=kernel)
@@ -492,24 +553,17 @@ def run_phen(args):
 
 
 def run_hgp64(args):
+    """64 hypergraph-product codes of seeded random (3,4)-regular classical codes (n from 400
+    to 6400), Poisson(2000) shots each in a seeded random order, p = 0.03, T = 100 + 100, in one
+    graph-captured multi-code launch whose threads per workgroup the plan's autotuner chose."""
     import torch
+    import oracle
     import paper_2510_08695_amd as P
     import synth
-    codes = synth.hgp_batch_codes(64, 4000, 0.03, with_logicals=False)
-    rng = np.random.default_rng(4)
-    counts = rng.poisson(2000, size=len(codes))
-    code_of_shot = np.concatenate([np.full(k, i, np.int32) for i, k in enumerate(counts)])
-    rng.shuffle(code_of_shot)
+    codes = synth.hgp_batch_codes(64, 4000, 0.03, with_logicals=True)
+    code_of_shot, syn_np, per = synth.mixed_batch(codes, 2000, 4, 4100)
     B = len(code_of_shot)
-    rows, per = [None] * B, []
-    for i, c in enumerate(codes):
-        idx = np.nonzero(code_of_shot == i)[0]
-        sh = synth.make_shots(c, len(idx), 4100 + i)
-        per.append((idx, sh))
-        packed = synth.pack_bits(sh.syndromes)
-        for k, b in enumerate(idx):
-            rows[b] = packed[k]
-    syn = torch.from_numpy(np.concatenate(rows).view(np.int64)).cuda()
+    syn = torch.from_numpy(syn_np).cuda()
     prm = P.Params(max_iter=(100, 100), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=4)
     t = time.perf_counter()
     handles = [P.Code.from_problem(c) for c in codes]
@@ -525,21 +579,50 @@ def run_hgp64(args):
     ms = _timed(lambda: plan.graph_launch(), args.steps, stream)
     it = iters.cpu().numpy().astype(np.int64)
     fl = flags.cpu().numpy()
-    ops = 0
+    corr_h, co_h = corr.cpu().numpy(), co.cpu().numpy()
+    ops, fails = 0, 0
     for i, c in enumerate(codes):
-        idx = per[i][0]
+        idx, sh = per[i]
         ops += OPS_PER_EDGE_ITER * c.H.nnz * int(it[idx].sum()) + OPS_PER_DC_ENTRY * c.D.nnz * int(((fl[idx] & 2) != 0).sum())
+        nwi = (c.n + 63) // 64
+        words = np.stack([corr_h[co_h[b]:co_h[b] + nwi] for b in idx]).view(np.uint64)
+        fails += int(round(_ler(c, sh.errors, words, fl[idx])[0] * len(idx)))
+    lo, hi = wilson(fails, B)
     res = {"metric": "shots/s BP+DC, 64 uneven HGP codes in one graph-captured persistent launch", "value": B / (ms / 1e3),
            "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "ms_per_step": ms, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"64 hypergraph-product codes of random (3,4)-regular codes, n in "
                                   f"[{min(c.n for c in codes)}, {max(c.n for c in codes)}], p=0.03, "
                                   f"Poisson(2000) shots each ({B} total), T=100+100",
-                      "plan_seconds": plan_s, "tile": {"threads": plan.info(int(np.argmax([c.n for c in codes])))["threads"]}},
+                      "plan_seconds": plan_s},
+           "autotune": plan.describe(-1),
+           "ler": fails / B, "ler_ci95": [lo, hi],
            "dc_rate": float(((fl & 2) != 0).mean()), "mean_iters": float(it.sum()) / B,
            "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                         "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
                         "traffic": committed_traffic("hgp64"), "traffic_unit": "bytes per launch",
                         "launch_ms": ms, "ops_per_launch": ops}}
+    if not args.no_cpu:
+        # the float64 oracle on the first shots of every code, for about --cpu-seconds in total
+        cores = len(os.sched_getaffinity(0))
+        op = oracle_params(prm, "channel")
+        done, el, f_cpu, f_gpu = 0, 0.0, 0, 0
+        per_code = max(1, int(64 * args.cpu_seconds))
+        for i, c in enumerate(codes):
+            idx, sh = per[i]
+            k = min(len(idx), max(1, per_code // 64))
+            t0 = time.perf_counter()
+            o = oracle.decode(c, sh.syndromes[:k], op, precision="f64", want_post=False, threads=cores)
+            el += time.perf_counter() - t0
+            f_cpu += int((((o["flags"] & 1) == 0) | synth.residual_is_logical(sh.errors[:k] ^ o["ehat"], c.O)).sum())
+            nwi = (c.n + 63) // 64
+            words = np.stack([corr_h[co_h[b]:co_h[b] + nwi] for b in idx[:k]]).view(np.uint64)
+            f_gpu += int(round(_ler(c, sh.errors[:k], words, fl[idx[:k]])[0] * k))
+            done += k
+        res["cpu_baseline"] = {"value": done / el, "unit": "shots/s", "cores": cores, "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"the first {done // 64} shots of each of the 64 codes, float64 oracle, "
+                                         f"{cores} OpenMP threads (tie draws hashed by position in the sample)",
+                               "ler_on_sample": f_cpu / done, "gpu_ler_on_sample": f_gpu / done}
     if not args.no_plain:
         # plain per-code launches over the same shots
         pplan = P.Plan(handles, prm, kernel=P.KERNEL_PLAIN)

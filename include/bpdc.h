@@ -128,16 +128,35 @@ bpdc_status bpdc_code_destroy(bpdc_code code);
 bpdc_status bpdc_code_info(bpdc_code code, int32_t* n, int32_t* m, int32_t* md, int32_t* edges);
 
 /* Build a plan for `ncodes` codes (they stay owned by the caller and must
- * outlive the plan).  `kernel` is a BPDC_KERNEL_* value; AUTO times the
- * available fused variants on the device and keeps the fastest (synchronous).
+ * outlive the plan); synchronous.  `kernel` is a BPDC_KERNEL_* value.  The
+ * plan's autotuner times candidate launch shapes on synthetic shots drawn
+ * from each code's own priors and keeps the fastest per shot:
+ *  - lane family: lanes per shot (1, 2 or 4, as the code's symmetry allows:
+ *    64, 32 or 16 shots per one-wave workgroup) x the largest claim of shots
+ *    a wave stages in LDS (8, 16 or 32), each a code-specialised compile
+ *    (cached on disk; bpdc_lane_precompile fills the cache);
+ *  - group family: threads per workgroup (64 ... 1024, one shot per
+ *    workgroup, its state in LDS);
+ *  - AUTO: when both fused families can run a code, both are tuned and the
+ *    faster per shot is kept; otherwise the one that can (else plain);
+ *  - the multi-code launch (more than one code): threads per workgroup timed
+ *    on a synthetic mixed batch of every code.
+ * bpdc_plan_describe reports the choices and the timings.
  * BPDC_ERR_UNSUPPORTED if the requested variant cannot run a code. */
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
                              int32_t kernel, bpdc_plan* out);
 bpdc_status bpdc_plan_destroy(bpdc_plan plan);
 /* The variant and tile a plan chose for code `code`: kernel (BPDC_KERNEL_*),
- * shots per workgroup, threads per workgroup. */
+ * shots per workgroup (lane: 64 / lanes per shot; group: 1; plain: 256, one
+ * shot per thread), threads per workgroup. */
 bpdc_status bpdc_plan_info(bpdc_plan plan, int32_t code, int32_t* kernel, int32_t* shots_per_wg,
                            int32_t* threads_per_wg);
+/* The autotuner's record for code `code` (or, with code = -1, the multi-code
+ * launch) as a JSON object written to buf (host, cap bytes, NUL-terminated,
+ * truncated to fit): the family and tile kept, why, and every candidate timed
+ * with its time per 1000 synthetic shots.  *needed (optional) gets the full
+ * length + 1. */
+bpdc_status bpdc_plan_describe(bpdc_plan plan, int32_t code, char* buf, size_t cap, size_t* needed);
 
 /* Diagnostics of degeneracy cutting (Appendix B: how flat are the posterior
  * profiles DC picks from; how many columns it cuts).  While a buffer is set,
@@ -245,7 +264,8 @@ bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
                               float* d_grad_w, void* stream);
 
 /* Compile, or find in the on-disk kernel cache, the code-specialised lane
- * kernel for (H, D) without touching a GPU (host-only; hipRTC).  The cache
+ * kernel for (H, D) -- every tile the plan autotuner may time -- without
+ * touching a GPU (host-only; hipRTC).  The cache
  * directory is $BPDC_CACHE_DIR, else kcache/ beside libbpdc.so.  posterior =
  * 1 for plans with BPDC_PRIOR_POSTERIOR; uniform_prior = 1 for codes whose
  * priors are all equal (the kernel then takes the prior as one value); rule

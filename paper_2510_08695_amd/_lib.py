@@ -27,7 +27,7 @@ EXPORTS = [
     "bpdc_plan_destroy", "bpdc_plan_info", "bpdc_workspace_size", "bpdc_decode",
     "bpdc_decode_multi", "bpdc_graph_capture_multi", "bpdc_graph_launch",
     "bpdc_wms_ckpt_size", "bpdc_wms_forward", "bpdc_wms_backward", "bpdc_lane_precompile",
-    "bpdc_plan_set_dc_stats", "bpdc_decode_noalloc",
+    "bpdc_plan_set_dc_stats", "bpdc_decode_noalloc", "bpdc_plan_describe",
     "bpdc_status_string", "bpdc_last_error", "bpdc_version",
 ]
 
@@ -81,6 +81,7 @@ def lib():
             "bpdc_lane_precompile": [C.POINTER(_Csr), C.POINTER(_Csr), I32, I32, I32, I32],
             "bpdc_plan_set_dc_stats": [P, P, I64],
             "bpdc_decode_noalloc": [P, I32, P, I64, I64, P, P, P, P, P, P],
+            "bpdc_plan_describe": [P, I32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -210,6 +211,16 @@ class Plan:
         k, s, t = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().bpdc_plan_info(self.handle, code, C.byref(k), C.byref(s), C.byref(t)))
         return {"kernel": k.value, "shots_per_wg": s.value, "threads": t.value}
+
+    def describe(self, code: int = 0) -> dict:
+        """The autotuner's record for `code` (-1: the multi-code launch): the tile kept and
+        every candidate timed (bpdc_plan_describe)."""
+        import json
+        need = C.c_size_t()
+        _check(lib().bpdc_plan_describe(self.handle, code, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(lib().bpdc_plan_describe(self.handle, code, buf, need.value, None))
+        return json.loads(buf.value.decode())
 
     def set_dc_stats(self, stats=None):
         """Accumulate DC diagnostics of later decodes into `stats` (int64 tensor of at least

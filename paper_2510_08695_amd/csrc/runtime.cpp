@@ -172,13 +172,15 @@ const Rtc& rtc() {
   return r;
 }
 
-// Compile (or load from the disk cache) the lane kernel for one code.
-bpdc_status lane_code_object(const std::string& spec, std::vector<char>* image, std::string* path_out) {
+// Compile (or load from the disk cache) the lane kernel for one code, with
+// `chunk` the largest number of shots a wave claims at once (the LDS staging
+// of their syndrome words).
+bpdc_status lane_code_object(const std::string& spec, int chunk, std::vector<char>* image, std::string* path_out) {
   std::string opts;
   for (int i = 0; i < kNumRtcOpts; ++i) opts += std::string(kRtcOpts[i]) + " ";
   std::string tune;
   if (const char* w = getenv("BPDC_LANE_WPE")) tune += "#define NB_WAVES_PER_EU " + std::string(w) + "\n";
-  if (const char* w = getenv("BPDC_LANE_CHUNK")) tune += "#define NB_CHUNK " + std::string(w) + "\n";
+  tune += "#define NB_CHUNK " + std::to_string(chunk) + "\n";
   const std::string full = "using u32 = unsigned int;\n" + std::string(kLaneDeviceSrc) + "\n" + tune + spec + "\n" +
                            std::string(kLaneKernelSrc);
   char key[32];
@@ -241,15 +243,24 @@ struct LaneKernel {
   hipFunction_t fn = nullptr;
   hipFunction_t prep = nullptr;  // syndrome preparation kernel of the same module
   int grid = 0;
-  int lanes = 1;                 // lanes per shot
+  int lanes = 1;                 // lanes per shot (64 / lanes shots per one-wave workgroup)
   int spw = 1;                   // prepared syndrome words per lane
+  int chunk = 16;                // largest claim of shots (LDS staging)
   std::string cache_path;
+};
+
+// One candidate the autotuner timed: what, and ms per 1000 synthetic shots.
+struct TuneTry {
+  std::string what;
+  double ms_per_kshot = -1.0;
 };
 
 struct CodePlan {
   int kernel = BPDC_KERNEL_PLAIN;
   LaneKernel lane;
   bpdc::GroupTile tile;
+  std::vector<TuneTry> tried;   // the autotuner's measurements (empty when it did not run)
+  std::string chose;
 };
 
 struct bpdc_plan_s {
@@ -266,6 +277,7 @@ struct bpdc_plan_s {
   bool multi_ok = false;
   std::string multi_why;
   bpdc::GroupTile multi_tile;
+  std::vector<TuneTry> multi_tried;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t* dcstats = nullptr;  // DC diagnostics buffer (bpdc_plan_set_dc_stats) or null
@@ -318,17 +330,19 @@ bool uniform_prior(const bpdc_code_s* c) {
   return true;
 }
 
-bpdc_status build_lane(bpdc_code c, bool posterior, int rule, bool soft, int num_cu, LaneKernel* lk) {
+bpdc_status build_lane(bpdc_code c, bool posterior, int rule, bool soft, int num_cu, int max_lanes, int chunk,
+                       LaneKernel* lk) {
   std::string why;
-  if (!bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why))
+  if (!bpdc::lane_eligible(c->g, posterior, max_lanes, rule, soft, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
   std::vector<char> image;
-  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), lane_max_lanes(), rule, soft);
+  const bpdc::LaneSpec spec = bpdc::lane_spec(c->g, posterior, uniform_prior(c), max_lanes, rule, soft);
   std::string src = spec.src;
-  bpdc_status st = lane_code_object(src, &image, &lk->cache_path);
+  bpdc_status st = lane_code_object(src, chunk, &image, &lk->cache_path);
   if (st != BPDC_OK) return st;
   lk->lanes = spec.lanes;
   lk->spw = spec.spw;
+  lk->chunk = chunk;
   HIP_TRY(hipModuleLoadData(&lk->mod, image.data()));
   HIP_TRY(hipModuleGetFunction(&lk->fn, lk->mod, "bpdc_lane_kernel"));
   HIP_TRY(hipModuleGetFunction(&lk->prep, lk->mod, "bpdc_lane_prepare"));
@@ -492,7 +506,8 @@ float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, Tu
 }
 
 bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::GroupTile* out,
-                              float* best_ms_out) {
+                              float* best_ms_out, std::vector<TuneTry>* tried = nullptr,
+                              double* best_ms_per_kshot = nullptr) {
   const bpdc::DevCode& d = p->codes[code]->dev;
   bpdc::GroupTile base;
   base.info_bytes = group_variant(p, d);
@@ -532,15 +547,157 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
     bpdc::GroupTile t = make(th);
     if (bpdc::group_occupancy(th, t.lds_bytes, t.info_bytes, p->max_lds) < 1) continue;
     const float ms = time_group(p, code, t, tb, S);
+    if (tried) {
+      TuneTry tt;
+      tt.what = "group " + std::to_string(th) + " threads, 1 shot/workgroup, " + std::to_string(t.lds_bytes) +
+                " B LDS per shot, " + std::to_string(t.grid / p->num_cu) + " workgroups/CU";
+      tt.ms_per_kshot = ms > 0 ? ms * 1000.0 / S : -1.0;
+      tried->push_back(tt);
+    }
     if (ms > 0 && (best < 0 || ms < best)) {
       best = ms;
       *out = t;
     }
   }
+  if (best_ms_per_kshot) *best_ms_per_kshot = best > 0 ? best * 1000.0 / S : -1.0;
   if (best < 0)
     return fail(BPDC_ERR_UNSUPPORTED, "no group tile could run code %d (lds %zu of %d bytes, last HIP error: %s)",
                 code, base.lds_bytes, p->max_lds, hipGetErrorString(hipGetLastError()));
   if (best_ms_out) *best_ms_out = best;
+  return BPDC_OK;
+}
+
+// ---- lane kernel: tile selection ----------------------------------------------------------
+
+// Lane-tile candidates of a code: the lane-group sizes its symmetry allows
+// (the largest, halved down to one lane per shot: 64, 32 or 16 shots per
+// one-wave workgroup) and the largest claim of shots (LDS staging of their
+// syndrome words).  BPDC_LANE_CHUNK pins the claim size.
+std::vector<std::pair<int, int>> lane_candidates(const bpdc::HostGraph& g, bool posterior, bool uniform, int rule,
+                                                 bool soft) {
+  std::vector<int> lanes;
+  for (int L = lane_max_lanes(); L >= 1; L /= 2) {
+    std::string why;
+    if (!bpdc::lane_eligible(g, posterior, L, rule, soft, &why)) continue;
+    const int got = bpdc::lane_spec(g, posterior, uniform, L, rule, soft).lanes;
+    if (std::find(lanes.begin(), lanes.end(), got) == lanes.end()) lanes.push_back(got);
+  }
+  std::vector<int> chunks = {8, 16, 32};
+  if (const char* e = getenv("BPDC_LANE_CHUNK")) chunks = {std::max(1, atoi(e))};
+  std::vector<std::pair<int, int>> out;
+  for (int L : lanes)
+    for (int ch : chunks) out.push_back({L, ch});
+  // the default tile (largest lane group, claims of 16) first: the tuner keeps it
+  // unless another is faster by more than the timing noise
+  std::stable_sort(out.begin(), out.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+    return (a.first == lanes[0] && a.second == 16) > (b.first == lanes[0] && b.second == 16);
+  });
+  return out;
+}
+
+struct LaneTuneBuffers {
+  uint64_t* syn = nullptr;
+  uint64_t* corr = nullptr;
+  uint8_t* flags = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  ~LaneTuneBuffers() {
+    if (syn) (void)hipFree(syn);
+    if (corr) (void)hipFree(corr);
+    if (flags) (void)hipFree(flags);
+    if (ws) (void)hipFree(ws);
+  }
+};
+
+// Time one decode of S synthetic shots with a lane tile (ms), negative if it fails.
+float time_lane(const bpdc_plan_s* p, const CodePlan& cp, bpdc_code c, LaneTuneBuffers& tb, int64_t S) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0f;
+  bpdc::DecodeIO io{tb.syn, S, 0, tb.corr, tb.flags, nullptr, nullptr, nullptr, nullptr};
+  float best = -1.0f;
+  for (int rep = 0; rep < 2; ++rep) {
+    (void)hipEventRecord(e0, 0);
+    const bpdc_status st = lane_launch(p, cp, c, io, tb.ws, 0);
+    (void)hipEventRecord(e1, 0);
+    if (st != BPDC_OK || hipEventSynchronize(e1) != hipSuccess) {
+      best = -1.0f;
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep == 1) best = ms;  // the first run warms caches and code
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+// Build the lane kernel of code `code` into cp.lane: with `autotune`, every
+// candidate tile is compiled (or found in the kernel cache) and timed on
+// synthetic shots drawn from the code's priors, and the fastest is kept;
+// otherwise the largest lane group with claims of 16.  *best_ms_per_kshot
+// gets the kept tile's time per 1000 shots (negative when not timed).
+bpdc_status choose_lane(bpdc_plan_s* p, int code, bool autotune, CodePlan* cp, double* best_ms_per_kshot) {
+  bpdc_code c = p->codes[code];
+  const bool posterior = p->kp.second_pass_posterior != 0, soft = p->kp.soft_period > 0;
+  const int rule = p->kp.rule;
+  if (best_ms_per_kshot) *best_ms_per_kshot = -1.0;
+  std::vector<std::pair<int, int>> cands = lane_candidates(c->g, posterior, uniform_prior(c), rule, soft);
+  if (cands.empty()) {
+    std::string why;
+    bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why);
+    return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run code %d: %s", code, why.c_str());
+  }
+  if (!autotune || cands.size() == 1) {
+    const int ch = getenv("BPDC_LANE_CHUNK") ? cands[0].second : 16;
+    return build_lane(c, posterior, rule, soft, p->num_cu, cands[0].first, ch, &cp->lane);
+  }
+  // enough shots for several rounds of the persistent grid (steady state, not the
+  // end of the batch), at most 64 MB of syndromes and corrections
+  const int sw = (c->g.m + 63) / 64, nw = (c->g.n + 63) / 64;
+  const int64_t S = std::max<int64_t>(8192, std::min<int64_t>(262144, (64ll << 20) / (8 * (sw + nw))));
+  LaneTuneBuffers tb;
+  const std::vector<uint64_t> hs = autotune_syndromes(c, (int)S, 0x1A4E0000ull + (uint64_t)code);
+  HIP_TRY(hipMalloc((void**)&tb.syn, hs.size() * 8));
+  HIP_TRY(hipMemcpy(tb.syn, hs.data(), hs.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMalloc((void**)&tb.corr, (size_t)S * nw * 8));
+  HIP_TRY(hipMalloc((void**)&tb.flags, (size_t)S));
+  (void)sw;
+  double best = -1.0;
+  cp->tried.clear();
+  for (const auto& cand : cands) {
+    CodePlan trial;
+    bpdc_status st = build_lane(c, posterior, rule, soft, p->num_cu, cand.first, cand.second, &trial.lane);
+    if (st != BPDC_OK) {
+      if (trial.lane.mod) (void)hipModuleUnload(trial.lane.mod);
+      continue;
+    }
+    const size_t need = lane_ws_bytes(trial.lane, S);
+    if (need > tb.ws_bytes) {
+      if (tb.ws) (void)hipFree(tb.ws);
+      tb.ws = nullptr;
+      HIP_TRY(hipMalloc(&tb.ws, need));
+      tb.ws_bytes = need;
+    }
+    trial.kernel = BPDC_KERNEL_LANE;
+    const float ms = time_lane(p, trial, c, tb, S);
+    TuneTry t;
+    t.what = "lane " + std::to_string(trial.lane.lanes) + " lanes/shot, " + std::to_string(64 / trial.lane.lanes) +
+             " shots/workgroup, claims of " + std::to_string(trial.lane.chunk);
+    t.ms_per_kshot = ms > 0 ? ms * 1000.0 / (double)S : -1.0;
+    cp->tried.push_back(t);
+    // a candidate replaces the one kept only when it is faster by more than 1 %
+    // (repeated timings of one tile differ by about that much)
+    if (ms > 0 && (best < 0 || t.ms_per_kshot < 0.99 * best)) {
+      best = t.ms_per_kshot;
+      if (cp->lane.mod) (void)hipModuleUnload(cp->lane.mod);
+      cp->lane = trial.lane;
+    } else if (trial.lane.mod) {
+      (void)hipModuleUnload(trial.lane.mod);
+    }
+  }
+  if (best < 0) return fail(BPDC_ERR_UNSUPPORTED, "no lane tile could run code %d", code);
+  if (best_ms_per_kshot) *best_ms_per_kshot = best;
   return BPDC_OK;
 }
 
@@ -573,7 +730,8 @@ size_t multi_ws_bytes(const bpdc_plan_s* p, int64_t B) {
 
 bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* syn, const int64_t* syn_off,
                           uint64_t* corr, const int64_t* corr_off, uint8_t* flags, int16_t* iters, int64_t B,
-                          int64_t shot_offset, void* ws, hipStream_t s) {
+                          int64_t shot_offset, void* ws, hipStream_t s, const bpdc::GroupTile* tile = nullptr) {
+  const bpdc::GroupTile& t = tile ? *tile : p->multi_tile;
   char* w = (char*)ws;
   unsigned long long* queue = (unsigned long long*)w;
   unsigned* hist = (unsigned*)(w + 256);
@@ -581,11 +739,114 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
   int32_t* order = (int32_t*)(w + 256 + 2 * align256((p->codes.size() + 1) * 4));
   HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, flags, s));
   HIP_TRY(bpdc::group_launch(p->d_code_table, hist + p->codes.size(), cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
-                             nullptr, iters, B, shot_offset, p->multi_tile.threads, p->multi_tile.grid,
-                             p->multi_tile.lds_bytes, p->multi_tile.info_bytes, queue, s));
+                             nullptr, iters, B, shot_offset, t.threads, t.grid, t.lds_bytes, t.info_bytes, queue, s));
   return BPDC_OK;
 }
 
+// Threads per workgroup of the multi-code launch: each candidate is timed on a
+// synthetic mixed batch (32 shots of every code drawn from its priors, codes
+// interleaved) and the fastest kept.  The LDS per workgroup is the largest
+// code's state either way.
+bpdc_status choose_multi_tile(bpdc_plan_s* p, const bpdc::GroupTile& base, const std::vector<int>& cands) {
+  const int nc = (int)p->codes.size();
+  const int per = 32;
+  const int64_t B = (int64_t)nc * per;
+  std::vector<std::vector<uint64_t>> syn_c(nc);
+  for (int i = 0; i < nc; ++i) syn_c[i] = autotune_syndromes(p->codes[i], per, 0x3C0D0000ull + (uint64_t)i);
+  std::vector<int32_t> cos((size_t)B);
+  std::vector<int64_t> so((size_t)B), co((size_t)B);
+  std::vector<uint64_t> syn;
+  int64_t sw_tot = 0, nw_tot = 0;
+  for (int k = 0; k < per; ++k)
+    for (int i = 0; i < nc; ++i) {
+      const int64_t b = (int64_t)k * nc + i;
+      const int sw = (p->codes[i]->g.m + 63) / 64, nw = (p->codes[i]->g.n + 63) / 64;
+      cos[b] = i;
+      so[b] = sw_tot;
+      co[b] = nw_tot;
+      syn.insert(syn.end(), syn_c[i].begin() + (size_t)k * sw, syn_c[i].begin() + (size_t)(k + 1) * sw);
+      sw_tot += sw;
+      nw_tot += nw;
+    }
+  struct Bufs {
+    void* p[7] = {};
+    ~Bufs() {
+      for (void* x : p)
+        if (x) (void)hipFree(x);
+    }
+  } d;
+  const size_t wsb = multi_ws_bytes(p, B);
+  HIP_TRY(hipMalloc(&d.p[0], cos.size() * 4));
+  HIP_TRY(hipMalloc(&d.p[1], so.size() * 8));
+  HIP_TRY(hipMalloc(&d.p[2], co.size() * 8));
+  HIP_TRY(hipMalloc(&d.p[3], syn.size() * 8));
+  HIP_TRY(hipMalloc(&d.p[4], (size_t)nw_tot * 8));
+  HIP_TRY(hipMalloc(&d.p[5], (size_t)B));
+  HIP_TRY(hipMalloc(&d.p[6], wsb));
+  HIP_TRY(hipMemcpy(d.p[0], cos.data(), cos.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d.p[1], so.data(), so.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d.p[2], co.data(), co.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d.p[3], syn.data(), syn.size() * 8, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = -1.0;
+  p->multi_tried.clear();
+  for (int th : cands) {
+    bpdc::GroupTile t = base;
+    t.threads = th;
+    const int nb = bpdc::group_occupancy(th, t.lds_bytes, t.info_bytes, p->max_lds);
+    if (nb < 1) continue;
+    t.grid = nb * p->num_cu;
+    float ms = -1.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, 0);
+      const bpdc_status st = multi_enqueue(p, (const int32_t*)d.p[0], (const uint64_t*)d.p[3], (const int64_t*)d.p[1],
+                                           (uint64_t*)d.p[4], (const int64_t*)d.p[2], (uint8_t*)d.p[5], nullptr, B, 0,
+                                           d.p[6], 0, &t);
+      (void)hipEventRecord(e1, 0);
+      if (st != BPDC_OK || hipEventSynchronize(e1) != hipSuccess) {
+        ms = -1.0f;
+        break;
+      }
+      (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    TuneTry tt;
+    tt.what = "multi-code " + std::to_string(th) + " threads, " + std::to_string(nb) + " workgroups/CU";
+    tt.ms_per_kshot = ms > 0 ? ms * 1000.0 / (double)B : -1.0;
+    p->multi_tried.push_back(tt);
+    if (ms > 0 && (best < 0 || tt.ms_per_kshot < best)) {
+      best = tt.ms_per_kshot;
+      p->multi_tile = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  if (best < 0) return fail(BPDC_ERR_UNSUPPORTED, "no multi-code tile could run");
+  return BPDC_OK;
+}
+
+}  // namespace
+
+namespace {
+std::string json_str(const std::string& x) {
+  std::string o = "\"";
+  for (char ch : x) {
+    if (ch == '"' || ch == '\\') o += '\\';
+    o += ch;
+  }
+  return o + "\"";
+}
+std::string json_tried(const std::vector<TuneTry>& v) {
+  std::string o = "[";
+  for (size_t k = 0; k < v.size(); ++k) {
+    char b[64];
+    snprintf(b, sizeof(b), "%.5g", v[k].ms_per_kshot);
+    o += (k ? ", " : "") + std::string("{\"candidate\": ") + json_str(v[k].what) + ", \"ms_per_1000_shots\": " + b + "}";
+  }
+  return o + "]";
+}
 }  // namespace
 
 extern "C" {
@@ -731,9 +992,15 @@ bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t p
     for (int k = D->row_ptr[r]; k < D->row_ptr[r + 1]; ++k) g.drows[r].push_back(D->col_idx[k]);
   if (!bpdc::lane_eligible(g, posterior != 0, lane_max_lanes(), rule, soft != 0, &why))
     return fail(BPDC_ERR_UNSUPPORTED, "lane kernel cannot run this code: %s", why.c_str());
-  std::vector<char> image;
-  return lane_code_object(
-      bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, lane_max_lanes(), rule, soft != 0).src, &image, nullptr);
+  // every tile the autotuner may time
+  for (const auto& cand : lane_candidates(g, posterior != 0, uniform_prior != 0, rule, soft != 0)) {
+    std::vector<char> image;
+    const bpdc_status st = lane_code_object(
+        bpdc::lane_spec(g, posterior != 0, uniform_prior != 0, cand.first, rule, soft != 0).src, cand.second, &image,
+        nullptr);
+    if (st != BPDC_OK) return st;
+  }
+  return BPDC_OK;
 }
 
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,
@@ -810,41 +1077,46 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     const bool soft = p->kp.soft_period > 0;
     const bool lane_ok = bpdc::lane_eligible(c->g, posterior, lane_max_lanes(), rule, soft, &why_lane);
     const bool group_ok = group_fits(p.get(), c->dev, &why_group);
-    if (rule == BPDC_RULE_PRODUCT_SUM && kernel == BPDC_KERNEL_AUTO) {
-      // product-sum: the lane kernel when the code fits one lane, else the
-      // group kernel when its rows and state fit, else plain
-      if (lane_ok) {
-        if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
-        cp.kernel = BPDC_KERNEL_LANE;
-      } else if (group_ok) {
-        if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
-        cp.kernel = BPDC_KERNEL_GROUP;
-      } else {
-        cp.kernel = BPDC_KERNEL_PLAIN;
-      }
-      continue;
-    }
     if (kernel == BPDC_KERNEL_LANE) {
-      if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+      if ((st = choose_lane(p.get(), i, true, &cp, nullptr)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
+      cp.chose = "lane (requested)";
       continue;
     }
     if (kernel == BPDC_KERNEL_GROUP) {
       if (!group_ok) return fail(BPDC_ERR_UNSUPPORTED, "group kernel cannot run code %d: %s", i, why_group.c_str());
-      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
+      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr, &cp.tried)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_GROUP;
+      cp.chose = "group (requested)";
       continue;
     }
-    // AUTO: the code-specialised lane kernel when the code fits one lane,
-    // otherwise the autotuned group kernel
-    if (lane_ok) {
-      if ((st = build_lane(c, posterior, rule, soft, p->num_cu, &cp.lane)) != BPDC_OK) return st;
+    // AUTO: when both fused families can run the code, each is autotuned on the
+    // same kind of synthetic shots and the faster per shot is kept; otherwise
+    // the one that can run it (product-sum codes too large for both: plain)
+    if (lane_ok && group_ok) {
+      double lane_ms = -1.0, group_ms = -1.0;
+      if ((st = choose_lane(p.get(), i, true, &cp, &lane_ms)) != BPDC_OK) return st;
+      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr, &cp.tried, &group_ms)) != BPDC_OK) return st;
+      if (group_ms > 0 && (lane_ms < 0 || group_ms < lane_ms)) {
+        if (cp.lane.mod) (void)hipModuleUnload(cp.lane.mod);
+        cp.lane = LaneKernel();
+        cp.kernel = BPDC_KERNEL_GROUP;
+        cp.chose = "group (faster than lane)";
+      } else {
+        cp.kernel = BPDC_KERNEL_LANE;
+        cp.chose = "lane (faster than group)";
+      }
+    } else if (lane_ok) {
+      if ((st = choose_lane(p.get(), i, true, &cp, nullptr)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_LANE;
+      cp.chose = "lane (group cannot run the code: " + why_group + ")";
     } else if (group_ok) {
-      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr)) != BPDC_OK) return st;
+      if ((st = choose_group_tile(p.get(), i, true, &cp.tile, nullptr, &cp.tried)) != BPDC_OK) return st;
       cp.kernel = BPDC_KERNEL_GROUP;
-    } else if (soft) {
-      cp.kernel = BPDC_KERNEL_PLAIN;  // soft DC on a code too large for one workgroup's LDS
+      cp.chose = "group (lane cannot run the code: " + why_lane + ")";
+    } else if (soft || rule == BPDC_RULE_PRODUCT_SUM) {
+      cp.kernel = BPDC_KERNEL_PLAIN;  // too large for one workgroup's LDS, or product-sum rows above 8
+      cp.chose = "plain (no fused family can run the code)";
     } else {
       return fail(BPDC_ERR_UNSUPPORTED, "no fused kernel for code %d (lane: %s; group: %s)", i, why_lane.c_str(),
                   why_group.c_str());
@@ -891,6 +1163,13 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
       const int nb = bpdc::group_occupancy(th, lds, info_bytes, p->max_lds);
       t.grid = std::max(1, nb) * p->num_cu;
       p->multi_tile = t;
+      if (ncodes > 1) {  // a mixed batch: time the thread counts on synthetic shots of every code
+        std::vector<int> cands;
+        for (int c2 : {256, 512, 1024})
+          if (c2 / 2 < maxw) cands.push_back(c2);
+        if (cands.empty()) cands.push_back(th);
+        if ((st = choose_multi_tile(p.get(), t, cands)) != BPDC_OK) return st;
+      }
     }
   }
   *out = p.release();
@@ -922,8 +1201,48 @@ bpdc_status bpdc_plan_info(bpdc_plan p, int32_t code, int32_t* kernel, int32_t* 
   if (!p || code < 0 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad plan/code");
   const CodePlan& cp = p->per_code[code];
   if (kernel) *kernel = cp.kernel;
-  if (shots_per_wg) *shots_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 : (cp.kernel == BPDC_KERNEL_GROUP ? 1 : 0);
-  if (threads_per_wg) *threads_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 : (cp.kernel == BPDC_KERNEL_GROUP ? cp.tile.threads : 256);
+  // the lane family runs one wave per workgroup holding 64 / lanes shots; the
+  // group family one shot per workgroup; the plain family one shot per thread
+  // of its 256-thread phase kernels
+  if (shots_per_wg)
+    *shots_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 / cp.lane.lanes : (cp.kernel == BPDC_KERNEL_GROUP ? 1 : 256);
+  if (threads_per_wg)
+    *threads_per_wg = cp.kernel == BPDC_KERNEL_LANE ? 64 : (cp.kernel == BPDC_KERNEL_GROUP ? cp.tile.threads : 256);
+  return BPDC_OK;
+}
+
+
+bpdc_status bpdc_plan_describe(bpdc_plan p, int32_t code, char* buf, size_t cap, size_t* needed) {
+  if (!p || code < -1 || code >= (int)p->per_code.size()) return fail(BPDC_ERR_INVALID_ARG, "bad plan/code");
+  std::string o;
+  if (code == -1) {
+    if (!p->multi_ok) {
+      o = "{\"multi_code\": false, \"why\": " + json_str(p->multi_why) + "}";
+    } else {
+      const bpdc::GroupTile& t = p->multi_tile;
+      o = "{\"multi_code\": true, \"threads_per_wg\": " + std::to_string(t.threads) +
+          ", \"shots_per_wg\": 1, \"lds_bytes_per_wg\": " + std::to_string(t.lds_bytes) +
+          ", \"workgroups\": " + std::to_string(t.grid) + ", \"tried\": " + json_tried(p->multi_tried) + "}";
+    }
+  } else {
+    const CodePlan& cp = p->per_code[code];
+    const char* fam = cp.kernel == BPDC_KERNEL_LANE ? "lane" : (cp.kernel == BPDC_KERNEL_GROUP ? "group" : "plain");
+    o = "{\"kernel\": \"" + std::string(fam) + "\", \"chose\": " + json_str(cp.chose);
+    if (cp.kernel == BPDC_KERNEL_LANE)
+      o += ", \"lanes_per_shot\": " + std::to_string(cp.lane.lanes) + ", \"shots_per_wg\": " +
+           std::to_string(64 / cp.lane.lanes) + ", \"threads_per_wg\": 64, \"claim_chunk\": " +
+           std::to_string(cp.lane.chunk) + ", \"workgroups\": " + std::to_string(cp.lane.grid);
+    else if (cp.kernel == BPDC_KERNEL_GROUP)
+      o += ", \"threads_per_wg\": " + std::to_string(cp.tile.threads) + ", \"shots_per_wg\": 1, \"lds_bytes\": " +
+           std::to_string(cp.tile.lds_bytes) + ", \"workgroups\": " + std::to_string(cp.tile.grid);
+    o += ", \"tried\": " + json_tried(cp.tried) + "}";
+  }
+  if (needed) *needed = o.size() + 1;
+  if (buf && cap > 0) {
+    const size_t k = std::min(cap - 1, o.size());
+    memcpy(buf, o.data(), k);
+    buf[k] = 0;
+  }
   return BPDC_OK;
 }
 

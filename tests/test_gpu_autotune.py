@@ -1,0 +1,85 @@
+"""The plan autotuner (GPU): lane tiles (lanes per shot, i.e. shots per workgroup, and the
+LDS staging of claimed shots), group tiles (threads per workgroup), AUTO's choice between
+the two fused families, and the multi-code launch's threads per workgroup.  Each decision
+is the fastest of the candidates it timed, the record lists them, and decoded results do
+not depend on the tile."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from gpu_helpers import assert_bit_exact, gpu_decode, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2510_08695_amd as P
+    P.lib()
+    return P
+
+
+def _fastest(tried, prefix):
+    t = [x for x in tried if x["candidate"].startswith(prefix) and x["ms_per_1000_shots"] > 0]
+    return min(t, key=lambda x: x["ms_per_1000_shots"]), t
+
+
+def test_auto_plan_tunes_lane_and_group_and_keeps_the_faster(P):
+    code = synth.bb_code("bb144", p=0.05)
+    prm = P.Params(max_iter=(100, 100), alpha=0.625, seed=1)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_AUTO)
+    d = plan.describe(0)
+    print("bb144 AUTO:", d, flush=True)
+    best_lane, lanes = _fastest(d["tried"], "lane")
+    best_group, groups = _fastest(d["tried"], "group")
+    # BB144's two half-block translations give lane groups of 4 and 2 (its state does not fit one
+    # lane), each with three claim sizes
+    assert len(lanes) == 6 and len(groups) >= 3
+    assert d["kernel"] == ("lane" if best_lane["ms_per_1000_shots"] <= best_group["ms_per_1000_shots"] else "group")
+    if d["kernel"] == "lane":
+        assert f"{d['lanes_per_shot']} lanes/shot" in best_lane["candidate"]
+        assert f"claims of {d['claim_chunk']}" in best_lane["candidate"]
+        info = plan.info(0)
+        assert info["kernel"] == P.KERNEL_LANE and info["shots_per_wg"] == 64 // d["lanes_per_shot"]
+
+
+def test_decode_does_not_depend_on_the_lane_tile(P, monkeypatch):
+    """Plans restricted (environment) to other tiles decode the same shots identically, and
+    like the float32 oracle."""
+    code = synth.bb_code("bb144", p=0.06)
+    sh = synth.make_shots(code, 3000, 77)
+    prm = P.Params(max_iter=(60, 60), alpha=0.625, seed=3)
+    c = P.Code.from_problem(code)
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "channel"), precision="f32", shot_offset=5)
+    seen = set()
+    for lanes, chunk in (("4", "16"), ("2", "8"), ("2", "32")):
+        monkeypatch.setenv("BPDC_LANE_MAX_LANES", lanes)
+        monkeypatch.setenv("BPDC_LANE_CHUNK", chunk)
+        plan = P.Plan([c], prm, kernel=P.KERNEL_LANE)
+        d = plan.describe(0)
+        seen.add((d["lanes_per_shot"], d["claim_chunk"]))
+        print(f"case lane tile {lanes} lanes, claims of {chunk}: {d['lanes_per_shot']}, {d['claim_chunk']}", flush=True)
+        assert_bit_exact(gpu_decode(plan, code, sh.syndromes, shot_offset=5), ref, code.n)
+    assert seen == {(4, 16), (2, 8), (2, 32)}
+
+
+def test_group_tile_record_and_multi_code_tile(P):
+    codes = [synth.hgp_code(synth.random_regular_classical(nc, 4100 + j), name=f"h{j}", p=0.05, with_logicals=False)
+             for j, nc in enumerate([16, 24, 32])]
+    prm = P.Params(max_iter=(30, 30), alpha=0.625, seed=4)
+    plan = P.Plan([P.Code.from_problem(c) for c in codes], prm, kernel=P.KERNEL_GROUP)
+    for i in range(3):
+        d = plan.describe(i)
+        best, groups = _fastest(d["tried"], "group")
+        assert d["kernel"] == "group" and len(groups) >= 3
+        assert best["candidate"].startswith(f"group {d['threads_per_wg']} threads")
+        assert plan.info(i)["threads"] == d["threads_per_wg"]
+    m = plan.describe(-1)
+    print("multi-code:", m, flush=True)
+    assert m["multi_code"] and len(m["tried"]) >= 2
+    best = min((x for x in m["tried"] if x["ms_per_1000_shots"] > 0), key=lambda x: x["ms_per_1000_shots"])
+    assert best["candidate"].startswith(f"multi-code {m['threads_per_wg']} threads")

@@ -93,7 +93,16 @@ def test_lane_kernel_generation_and_compilation(P, tmp_path, monkeypatch):
     c = synth.toric_code(4)
     P.lane_precompile(c.H, c.D, posterior=True)
     files = list(tmp_path.iterdir())
-    assert len(files) == 1 and files[0].stat().st_size > 1000
+    # every tile the plan autotuner may time: the toric code's translations give lane
+    # groups of 4, 2 and 1 lanes per shot, each with claims of 8, 16 and 32 shots
+    assert len(files) == 9 and all(f.stat().st_size > 1000 for f in files)
+    # compiling again finds them all in the cache
+    P.lane_precompile(c.H, c.D, posterior=True)
+    assert len(list(tmp_path.iterdir())) == 9
+    monkeypatch.setenv("BPDC_LANE_CHUNK", "16")
+    monkeypatch.setenv("BPDC_LANE_MAX_LANES", "2")
+    P.lane_precompile(c.H, c.D, posterior=True)
+    assert len(list(tmp_path.iterdir())) == 9    # (2 lanes, 16) and (1 lane, 16) were cached already
     # a code too large for one lane per shot is refused, not compiled
     big = synth.hgp_code(synth.random_regular_classical(16, 4001), with_logicals=False)
     with pytest.raises(P.BpdcError, match="unsupported"):
