@@ -115,7 +115,11 @@ typedef struct bpdc_plan_s* bpdc_plan; /* launch configuration for one or more c
 
 /* Load a decoding problem: Tanner graph H (m x n), degeneracy matrix D
  * (m' x n, same n) and per-column prior error probabilities h_priors[n], each
- * in (0, 1).  The prior LLRs log((1-p)/p) are evaluated in double and rounded
+ * in (0, 1).  These are Algorithm 1's inputs (Sec. III.A): H = H_Z, whose
+ * syndrome is decoded, D = H_X, whose rows nominate the columns to cut, and the
+ * channel error probability p of each column (code capacity, Sec. II.C); for
+ * a detector error model (Sec. IV.B) H is the detector check matrix, D the
+ * detector degeneracy matrix and p the probability of each fault mechanism.  The prior LLRs log((1-p)/p) are evaluated in double and rounded
  * once to float.  Copies everything to the current device; synchronous.
  * Row degree of H is limited to 64, column degree of H to 16, row degree of D
  * to 32 (BPDC_ERR_UNSUPPORTED otherwise); the group kernel family runs rows
@@ -178,7 +182,12 @@ bpdc_status bpdc_plan_set_dc_stats(bpdc_plan plan, uint64_t* d_stats, int64_t wo
  * code `code` (bpdc_decode_multi: pass code = -1 and the total batch). */
 bpdc_status bpdc_workspace_size(bpdc_plan plan, int32_t code, int64_t B, size_t* bytes);
 
-/* Decode B shots of code `code` (index into the plan's code list).
+/* Decode B shots of code `code` (index into the plan's code list): Algorithm 1
+ * (Sec. III.A) per shot -- BP_decode on the syndrome (Sec. II.C: flooding
+ * updates, hard decision e = [p >= 1/2] of Eq. (3), stop once H e = s), and on
+ * shots where it fails, degeneracy cutting over the rows of D and a second
+ * BP_decode on the cut graph with the cut columns at prior probability 0
+ * (Algorithm 2); the outputs are BP_decode's estimate and posteriors.
  *   d_syn   [B][ceil(m/64)] uint64 packed syndromes (input)
  *   d_corr  [B][ceil(n/64)] uint64 packed corrections e_hat (output; cut columns are 0)
  *   d_flags [B] uint8: bit 0 = H e_hat = s, bit 1 = DC ran (output)
