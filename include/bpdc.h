@@ -61,7 +61,10 @@ enum { BPDC_TIE_HASH = 0, BPDC_TIE_LOWEST_INDEX = 1 };
  * r = alpha * min over the other |q|, or product-sum,
  * r = alpha * 2 atanh(prod over the other tanh(|q| / 2)) (alpha = 1 for the
  * plain rule), each saturated at llr_sat and signed by the syndrome bit and
- * the other signs.  Product-sum runs on the plain kernel family, on the lane
+ * the other signs.  Product-sum is evaluated in the log domain,
+ * r = alpha * phi(sum over the other phi(|q|)) with phi(x) = -ln tanh(x / 2),
+ * the same function without the rounding of a product of tanh values to 1;
+ * a cut column (prior probability 0) sends +inf, i.e. phi = 0.  Product-sum runs on the plain kernel family, on the lane
  * family for codes of at most 96 edges (one lane per shot) and on the group
  * family for rows of at most 8 edges; not in the multi-code launch or
  * weighted decoding. */
@@ -283,6 +286,11 @@ bpdc_status bpdc_wms_backward(bpdc_plan plan, int32_t code, const float* d_w,
  * BPDC_ERR_UNSUPPORTED if the code is too large for the lane kernel. */
 bpdc_status bpdc_lane_precompile(const bpdc_csr* H, const bpdc_csr* D, int32_t posterior,
                                  int32_t uniform_prior, int32_t rule, int32_t soft);
+
+/* The library's float32 phi(x) = ln((e^x + 1) / (e^x - 1)) = -ln tanh(x / 2)
+ * (the product-sum rule's function, x >= 0 or +inf) on n floats: d_out[i] =
+ * phi(d_x[i]), device arrays, enqueued on `stream`.  For accuracy tests. */
+bpdc_status bpdc_eval_phi(const float* d_x, int64_t n, float* d_out, void* stream);
 
 const char* bpdc_status_string(bpdc_status status);
 const char* bpdc_last_error(void);

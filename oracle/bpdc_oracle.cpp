@@ -126,6 +126,16 @@ Real sat(Real x, Real lsat) {
   return std::min(std::max(x, -lsat), lsat);
 }
 
+// phi(x) = ln((e^x + 1) / (e^x - 1)) = -ln tanh(x / 2) for x >= 0, written
+// log1p(2 / expm1(x)): phi(0) = +inf, phi(+inf) = 0, and phi is its own
+// inverse.  The product-sum message 2 atanh(prod tanh(|q| / 2)) equals
+// phi(sum phi(|q|)) (the log of the product is minus the sum of the phi), and
+// in this form neither side rounds to 1 near saturation.
+template <class Real>
+Real phi(Real x) {
+  return std::log1p(Real(2) / std::expm1(x));
+}
+
 template <class Real>
 struct PassOut {
   std::vector<unsigned char> ehat;  // hard decision
@@ -185,9 +195,11 @@ PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vecto
   out.ehat.assign(g.n, 0);
   out.L.assign(g.n, 0);
 
-  // variable-to-check messages of the first iteration: the prior LLR
+  // variable-to-check messages of the first iteration: the prior LLR.  A
+  // frozen column (prior probability 0) sends +inf: no minimum or sum over a
+  // check moves because of it, exactly as if its column were deleted
   for (int v = 0; v < g.n; ++v)
-    for (int e : g.var_edges[v]) q[e] = frozen[v] ? lsat : sat(prior[v], lsat);
+    for (int e : g.var_edges[v]) q[e] = frozen[v] ? (Real)INFINITY : sat(prior[v], lsat);
 
   auto syndrome_ok = [&]() {
     for (int c = 0; c < g.m; ++c) {
@@ -227,11 +239,14 @@ PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vecto
           r[e] = negative ? -val : val;
         }
       } else {
+        // product-sum in the log domain: the sum of phi(|q|) over the other edges,
+        // left to right in row order, then phi of that sum (an empty sum, or one of
+        // zeros from frozen columns, gives +inf: the magnitude is held at lsat)
         for (int e = b; e < f; ++e) {
-          Real prod = 1;
+          Real sum = 0;
           for (int o = b; o < f; ++o)
-            if (o != e) prod = prod * std::tanh(std::fabs(q[o]) / 2);
-          Real mag = 2 * std::atanh(prod);
+            if (o != e) sum = sum + phi(std::fabs(q[o]));
+          Real mag = phi(sum);
           if (!(mag < lsat)) mag = lsat;
           const Real val = (w ? w[e] : alpha) * mag;
           const bool negative = neg ^ (q[e] < 0);
@@ -242,7 +257,7 @@ PassOut<Real> bp_decode(const Graph& g, const unsigned char* s, const std::vecto
     // posteriors, next variable-to-check messages, hard decision
     for (int v = 0; v < g.n; ++v) {
       if (frozen[v]) {
-        for (int e : g.var_edges[v]) q[e] = lsat;
+        for (int e : g.var_edges[v]) q[e] = (Real)INFINITY;
         L[v] = INFINITY;
         out.ehat[v] = 0;
         continue;

@@ -27,7 +27,7 @@ EXPORTS = [
     "bpdc_plan_destroy", "bpdc_plan_info", "bpdc_workspace_size", "bpdc_decode",
     "bpdc_decode_multi", "bpdc_graph_capture_multi", "bpdc_graph_launch",
     "bpdc_wms_ckpt_size", "bpdc_wms_forward", "bpdc_wms_backward", "bpdc_lane_precompile",
-    "bpdc_plan_set_dc_stats", "bpdc_decode_noalloc", "bpdc_plan_describe",
+    "bpdc_plan_set_dc_stats", "bpdc_decode_noalloc", "bpdc_plan_describe", "bpdc_eval_phi",
     "bpdc_status_string", "bpdc_last_error", "bpdc_version",
 ]
 
@@ -82,6 +82,7 @@ def lib():
             "bpdc_plan_set_dc_stats": [P, P, I64],
             "bpdc_decode_noalloc": [P, I32, P, I64, I64, P, P, P, P, P, P],
             "bpdc_plan_describe": [P, I32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
+            "bpdc_eval_phi": [P, I64, P, P],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -387,6 +388,15 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def eval_phi(x):
+    """The library's float32 phi(x) = -ln tanh(x/2) (product-sum) on a float32 CUDA tensor."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_cuda and x.is_contiguous()
+    out = torch.empty_like(x)
+    _check(lib().bpdc_eval_phi(_ptr(x), x.numel(), _ptr(out), _stream()))
+    return out
 
 
 def weighted_bpdc(plan: "Plan", code: int = 0, ckpt_every: int = 5):

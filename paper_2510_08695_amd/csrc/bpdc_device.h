@@ -94,35 +94,48 @@ __device__ __forceinline__ int spread_bin(const float* vals, int deg) {
   return bin < 0 ? 0 : (bin > 100 ? 100 : bin);
 }
 
-// Product-sum rule (Sec. II.C) in float32, written from the identities
-//   tanh(x/2) = (1 - e) / (1 + e),   e = exp(-x) = 2^(-x log2 e),
-//   2 atanh(p) = ln((1 + p) / (1 - p)) = ln 2 * log2((1 + p) / (1 - p)),
-// with the hardware exp2 / log2 / reciprocal (about 1 ulp each), and below
-// the points where those forms cancel (x < 1/2, p < 1/4) the odd Taylor
-// series of tanh(x/2) and of 2 atanh(p), whose first omitted terms are below
-// 1e-8 relative there.  Accurate to a few ulp, about 15 instructions each;
-// every GPU product-sum decoder uses these two functions.
-__device__ __forceinline__ float tanh_half(float x) {  // x >= 0
+// Product-sum rule (Sec. II.C) in the log domain: with
+//   phi(x) = -ln tanh(x / 2) = ln((e^x + 1) / (e^x - 1))   (x >= 0),
+// an involution with phi(0) = +inf and phi(+inf) = 0, the message
+// 2 atanh(prod tanh(|q| / 2)) equals phi(sum phi(|q|)).  Unlike the product of
+// tanh values, which rounds to 1 long before the messages saturate, both sums
+// and phi keep their relative precision at every magnitude.  float32 phi from
+// the hardware exp2 / log2 / reciprocal (about 1 ulp each), in three ranges:
+//   x < 1/2:   -ln(x/2) + y^2/3 - 7y^4/90 + 62y^6/2835 - 127y^8/18900 (y = x/2;
+//              the Taylor series of -ln(tanh(y)/y), Bernoulli-number coefficients);
+//   1/2 <= x < 2:  ln((1 + e) / (1 - e)),  e = e^-x  (1 - e >= 0.39: no cancellation);
+//   x >= 2:    2 atanh(e) = 2e (1 + e^2/3 + e^4/5 + e^6/7 + e^8/9)  (e <= 0.136).
+// Every GPU product-sum decoder uses this function; a cut column sends +inf
+// (prior probability 0), whose phi is 0.
+__device__ __forceinline__ float phi(float x) {  // x >= 0 or +inf
   const float y = 0.5f * x, y2 = y * y;
-  float s = fmaf(y2, 62.0f / 2835.0f, -17.0f / 315.0f);
-  s = fmaf(s, y2, 2.0f / 15.0f);
-  s = fmaf(s, y2, -1.0f / 3.0f);
-  s = fmaf(s, y2, 1.0f);
-  const float series = y * s;
-  const float e = __builtin_amdgcn_exp2f(-fminf(x, 64.0f) * 1.44269504088896341f);
-  const float direct = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
-  return x < 0.5f ? series : direct;
+  float ps = fmaf(y2, -127.0f / 18900.0f, 62.0f / 2835.0f);
+  ps = fmaf(ps, y2, -7.0f / 90.0f);
+  ps = fmaf(ps, y2, 1.0f / 3.0f);
+  ps = ps * y2;
+  // e = e^-x = 2^-(x log2 e): t = x log2 e rounded, with its rounding error d
+  // (fma) and the constant's own (x times log2 e - its float value), and
+  // 2^-d = 1 - d ln 2 to first order (|d| < 2^-17), so the exponent's rounding
+  // does not scale with x; beyond x = 128 (+inf included) e underflows to 0
+  const float xc = fminf(x, 128.0f);
+  const float t = xc * 1.44269504088896341f;
+  const float d = fmaf(xc, 1.44269504088896341f, -t) + xc * 1.9259629911e-8f;
+  const float e = __builtin_amdgcn_exp2f(-t) * fmaf(-d, 0.693147180559945309f, 1.0f);
+  const float e2 = e * e;
+  float pl = fmaf(e2, 1.0f / 9.0f, 1.0f / 7.0f);
+  pl = fmaf(pl, e2, 1.0f / 5.0f);
+  pl = fmaf(pl, e2, 1.0f / 3.0f);
+  pl = fmaf(pl, e2, 1.0f);
+  const float large = 2.0f * e * pl;
+  const float arg = (x < 0.5f) ? y : (1.0f + e) * __builtin_amdgcn_rcpf(1.0f - e);
+  const float lg = __builtin_amdgcn_logf(arg) * 0.693147180559945309f;  // ln(arg)
+  return (x < 0.5f) ? ps - lg : ((x < 2.0f) ? lg : large);
 }
-__device__ __forceinline__ float atanh2(float p) {  // 2 atanh(p), 0 <= p <= 1 (+inf at 1)
-  const float p2 = p * p;
-  float s = fmaf(p2, 1.0f / 11.0f, 1.0f / 9.0f);
-  s = fmaf(s, p2, 1.0f / 7.0f);
-  s = fmaf(s, p2, 1.0f / 5.0f);
-  s = fmaf(s, p2, 1.0f / 3.0f);
-  s = fmaf(s, p2, 1.0f);
-  const float series = 2.0f * p * s;
-  const float direct = __builtin_amdgcn_logf((1.0f + p) * __builtin_amdgcn_rcpf(1.0f - p)) * 0.693147180559945309f;
-  return p < 0.25f ? series : direct;
+
+// q of a product-sum edge: sat(L - r), except +inf from a cut column (L = +inf).
+__device__ __forceinline__ float ps_q(float L, float r, float lsat) {
+  const float x = L - r;
+  return (x == __builtin_huge_valf()) ? x : sat(x, lsat);
 }
 
 }  // namespace bpdc_dev

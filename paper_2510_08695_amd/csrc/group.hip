@@ -150,9 +150,10 @@ __device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg,
 // 1.3-1.5x over the 128-register build, whose single workgroup per CU stalls
 // the unit at every barrier; the few spills are outside the inner loops).
 // PS: the product-sum rule (Sec. II.C), rows of at most 8 edges: per-edge r
-// in LDS instead of check records, the leave-one-out products of tanh(|q|/2)
-// left to right in row order and the column sums in ascending check order,
-// with bpdc_device.h's float32 tanh / atanh, as in the plain and lane kernels.
+// in LDS instead of check records, in the log domain (phi of the leave-one-out
+// sums of phi(|q|), left to right in row order) and the column sums in
+// ascending check order, with bpdc_device.h's float32 phi, as in the plain and
+// lane kernels.
 template <bool Wide, bool PS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_group(GArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -267,28 +268,29 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             const int e0 = gload(C.h_row_ptr, c), deg = gload(C.h_row_ptr, c + 1) - e0;
             const u32 sbit = (synw[c >> 5] >> (c & 31)) & 1u;
             u32 par = sbit, neg = sbit, qn = 0u;
-            float th[8];
+            float ph[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-              th[j] = 1.0f;
+              ph[j] = 0.0f;
               if (j < deg) {
                 const float Lv = L[gload(C.h_col, e0 + j)];
                 par ^= (Lv <= 0.0f) ? 1u : 0u;
-                const float q = bpdc_dev::sat(Lv - R[e0 + j], LS);
+                const float q = bpdc_dev::ps_q(Lv, R[e0 + j], LS);  // +inf from a cut column
                 const u32 qneg = (q < 0.0f) ? 1u : 0u;
                 neg ^= qneg;
                 qn |= qneg << j;
-                th[j] = bpdc_dev::tanh_half(fabsf(q));
+                ph[j] = bpdc_dev::phi(fabsf(q));
               }
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               if (j < deg) {
-                float prod = 1.0f;
+                // phi of the sum of the other edges' phi, left to right in row order
+                float sum = 0.0f;
 #pragma unroll
                 for (int o = 0; o < 8; ++o)
-                  if (o != j && o < deg) prod = prod * th[o];
-                float mag = bpdc_dev::atanh2(prod);
+                  if (o != j && o < deg) sum = sum + ph[o];
+                float mag = bpdc_dev::phi(sum);
                 if (!(mag < LS)) mag = LS;
                 const float val = P.alpha * mag;
                 R[e0 + j] = (neg ^ ((qn >> j) & 1u)) ? -val : val;

@@ -121,6 +121,9 @@ hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, cons
                         const float* gpost, const uint64_t* cut, const uint8_t* flags, const void* ckpt, float* gw,
                         int num_cu, int max_lds, hipStream_t stream);
 
+// bpdc_device.h's product-sum function phi on n floats (accuracy tests).
+hipError_t eval_phi(const float* x, int64_t n, float* out, hipStream_t stream);
+
 // Small fill kernel (graph-capture safe replacement for hipMemsetAsync).
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream);
 

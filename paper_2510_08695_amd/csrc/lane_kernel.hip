@@ -131,11 +131,11 @@ __device__ __forceinline__ float xchgf(float x) {
   return __uint_as_float(xchgu<J>(__float_as_uint(x)));
 }
 
-// Product-sum check output: the atanh of the leave-one-out product of
-// tanh(|q|/2), doubled and saturated (atanh(1) = +inf becomes lsat), scaled,
-// with the sign bit `neg`.
-__device__ __forceinline__ float ps_r(float prod, u32 neg, float alpha, float lsat) {
-  float mag = bpdc_dev::atanh2(prod);
+// Product-sum check output from the leave-one-out sum of phi(|q|): phi of the
+// sum, saturated (an empty sum gives phi(0) = +inf, which becomes lsat),
+// scaled, with the sign bit `neg`.
+__device__ __forceinline__ float ps_r(float sum, u32 neg, float alpha, float lsat) {
+  float mag = bpdc_dev::phi(sum);
   mag = (mag < lsat) ? mag : lsat;
   return __uint_as_float(__float_as_uint(alpha * mag) ^ (neg << 31));
 }
@@ -169,21 +169,21 @@ __device__ __forceinline__ long long readlane64(long long x, int src) {
 // ev), starting from the check's syndrome bit.
 #define NB_EP0(s, ev) ep_##s = (ev) ^ (S[(s) >> 5] << (31 - ((s) & 31)))
 #define NB_EP(s, ev) ep_##s ^= (ev)
-// Product-sum rule (NB_PS, one lane per shot): an edge's register R[k] takes
-// tanh(|q| / 2) once its column is swept, and the sign of q goes to bit b of
-// the check's sign word; at the check's last edge NB_PSR forms each new
-// r = sign * alpha * min(2 atanh(product of the other edges' values), lsat).
+// Product-sum rule (NB_PS, one lane per shot), in the log domain: an edge's
+// register R[k] takes phi(|q|) once its column is swept, and the sign of q
+// goes to bit b of the check's sign word; at the check's last edge NB_PSR
+// forms each new r = sign * alpha * min(phi(sum of the other edges' values), lsat).
 #define NB_PSACC0(s, k, b, q)                                  \
   {                                                            \
-    R[k] = bpdc_dev::tanh_half(fabsf(q));                      \
+    R[k] = bpdc_dev::phi(fabsf(q));                            \
     sb_##s = (__float_as_uint(q) >> 31) << (b);                \
   }
 #define NB_PSACC(s, k, b, q)                                   \
   {                                                            \
-    R[k] = bpdc_dev::tanh_half(fabsf(q));                      \
+    R[k] = bpdc_dev::phi(fabsf(q));                            \
     sb_##s |= (__float_as_uint(q) >> 31) << (b);               \
   }
-#define NB_PSR(prod, neg) bpdc_lane::ps_r((prod), (neg), alpha, LS)
+#define NB_PSR(sum, neg) bpdc_lane::ps_r((sum), (neg), alpha, LS)
 // Complete slot s (degree d, field at bit `off` of W[cw]): r signs =
 // s_c xor parity of all q signs xor own sign; stop-test parity into U.  Only
 // bit 31 of ev, ep and U is meaningful: ep starts as the check's syndrome bit
@@ -301,7 +301,7 @@ extern "C" __global__ void NB_KATTR bpdc_lane_kernel(LaneArgs a) {
   const u64 leaders = NB_G == 4 ? 0x1111111111111111ull : (NB_G == 2 ? 0x5555555555555555ull : ~0ull);
 
 #if NB_PS
-  float R[NB_NR];  // per edge: r, or tanh(|q|/2) once its column is swept
+  float R[NB_NR];  // per edge: r, or phi(|q|) once its column is swept
 #else
   float A1[NB_SLOTS], A2[NB_SLOTS];
   u32 W[NB_NWC];

@@ -309,9 +309,9 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
     // Product-sum (one lane per shot): one register R[k] per edge, k running
     // over the checks (slots) and, within a check, its columns in ascending
     // order.  R[k] holds the edge's r until its column is swept, then
-    // tanh(|q| / 2); at the check's last edge the new r of every edge is
-    // formed from them (leave-one-out products left to right in column
-    // order, 2 atanh, saturation, sign) and written back.
+    // phi(|q|); at the check's last edge the new r of every edge is formed
+    // from them (leave-one-out sums left to right in column order, phi,
+    // saturation, sign) and written back.
     std::vector<int> rbase(nslots + 1, 0);
     for (int sl = 0; sl < nslots; ++sl) rbase[sl + 1] = rbase[sl] + (int)g.rows[slot_base[sl]].size();
     o << "#define NB_NR " << std::max(1, rbase[nslots]) << "\n";
@@ -333,10 +333,10 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
       o << "NB_CUT(L, " << i << "); NB_STORE(" << row_col[i] << ", L); const u32 ev = __float_as_uint(L) - 1u; \\\n";
       for (int j = 0; j < dv; ++j) {
         const int sl = e[j].slot, d = (int)g.rows[slot_base[sl]].size();
-        // q = sat(L - r) as Sec. II.C's product-sum takes it: unlike min-sum, tanh(|q| / 2)
-        // sees |q| itself, so a cut column (L = +inf) must send exactly +lsat and a
-        // posterior beyond lsat must be held there before tanh.
-        o << "{ const float q = bpdc_dev::sat(L - r" << j << ", LS); " << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << sl << ", ev); "
+        // q = sat(L - r), +inf from a cut column (L = +inf): unlike min-sum, phi sees
+        // |q| itself, so a posterior beyond lsat is held there and a cut column
+        // contributes phi(+inf) = 0.
+        o << "{ const float q = bpdc_dev::ps_q(L, r" << j << ", LS); " << (pos[i][j] == 0 ? "NB_EP0(" : "NB_EP(") << sl << ", ev); "
           << (pos[i][j] == 0 ? "NB_PSACC0(" : "NB_PSACC(") << sl << ", " << kk[j] << ", " << bb[j] << ", q); } \\\n";
         if (pos[i][j] == sdeg[sl] - 1) {
           // finalise check slot sl: d edges in registers rbase[sl] ..
@@ -345,13 +345,13 @@ LaneSpec lane_spec(const HostGraph& g, bool posterior, bool uniform_prior, int m
             << ")) & 1u; ";
           for (int b = 0; b < d; ++b) o << "const float t" << b << "_ = R[" << k0 + b << "]; ";
           for (int b = 0; b < d; ++b) {
-            std::string prod;
+            std::string sum;
             for (int x = 0; x < d; ++x) {
               if (x == b) continue;
-              prod = prod.empty() ? "t" + std::to_string(x) + "_" : "(" + prod + ") * t" + std::to_string(x) + "_";
+              sum = sum.empty() ? "t" + std::to_string(x) + "_" : "(" + sum + ") + t" + std::to_string(x) + "_";
             }
-            if (prod.empty()) prod = "1.0f";
-            o << "R[" << k0 + b << "] = NB_PSR(" << prod << ", par_ ^ ((sb_" << sl << " >> " << b << ") & 1u)); ";
+            if (sum.empty()) sum = "0.0f";
+            o << "R[" << k0 + b << "] = NB_PSR(" << sum << ", par_ ^ ((sb_" << sl << " >> " << b << ") & 1u)); ";
           }
           o << "U |= ep_" << sl << "; } \\\n";
         }

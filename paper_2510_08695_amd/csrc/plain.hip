@@ -58,36 +58,39 @@ __global__ void k_init_state(unsigned char* st, short* it, int64_t B) {
   it[2 * b + 1] = 0;
 }
 
-// First-iteration messages of a pass: q_{v->c} = sat(prior_v) (+lsat on cut columns).
+// First-iteration messages of a pass: q_{v->c} = sat(prior_v), +inf on cut
+// columns (prior probability 0: never a minimum, phi(+inf) = 0 in a sum).
 __global__ void k_init_msgs(DevCode c, PlainWs w, int64_t B, int pass, float lsat) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   if (b >= B) return;
   if (w.st[b] != (pass ? ST_PASS2 : ST_PASS1)) return;
   const float lam = pass ? w.lam2[(size_t)v * B + b] : c.lam[v];
-  const float q0 = bpdc_dev::sat(lam, lsat);
+  const float q0 = (lam == __builtin_huge_valf()) ? lam : bpdc_dev::sat(lam, lsat);
   for (int k = c.h_col_ptr[v]; k < c.h_col_ptr[v + 1]; ++k) w.q[(size_t)c.h_col_edge[k] * B + b] = q0;
 }
 
 // Check half, product-sum rule (Sec. II.C): r_{c->v} = sign * alpha *
-// 2 atanh(product over the other edges of tanh(|q| / 2)), the product taken
-// left to right in row order; the magnitude saturates at lsat (atanh(1) is
-// +inf).  Sign as for min-sum.  At most 32 edges per check (plan creation
-// refuses product-sum on longer rows).
-// tanh and atanh are bpdc_device.h's float32 forms, shared with the lane kernel.
+// 2 atanh(product over the other edges of tanh(|q| / 2)), evaluated in the
+// log domain as phi(sum over the other edges of phi(|q|)), the sum taken left
+// to right in row order; the magnitude saturates at lsat (an empty sum gives
+// phi(0) = +inf).  Sign as for min-sum.  At most 32 edges per check (plan
+// creation refuses product-sum on longer rows).  phi is bpdc_device.h's
+// float32 form, shared with the lane and group kernels.
 __device__ void check_product_sum(const DevCode& c, const PlainWs& w, int64_t B, int64_t b, int e0, int e1,
                                   u32 neg, float alpha, float lsat) {
-  float th[32];
+  float ph[32];
   for (int e = e0; e < e1; ++e) {
     const float q = w.q[(size_t)e * B + b];
     neg ^= (q < 0.0f) ? 1u : 0u;
-    th[e - e0] = bpdc_dev::tanh_half(fabsf(q));
+    ph[e - e0] = bpdc_dev::phi(fabsf(q));
   }
   for (int e = e0; e < e1; ++e) {
-    float prod = 1.0f;
+    // phi of the sum of the other edges' phi, left to right in row order
+    float sum = 0.0f;
     for (int o = e0; o < e1; ++o)
-      if (o != e) prod = prod * th[o - e0];
-    float mag = bpdc_dev::atanh2(prod);
+      if (o != e) sum = sum + ph[o - e0];
+    float mag = bpdc_dev::phi(sum);
     if (!(mag < lsat)) mag = lsat;
     const float val = alpha * mag;
     const float q = w.q[(size_t)e * B + b];
@@ -143,8 +146,8 @@ __global__ void k_var(DevCode c, PlainWs w, int64_t B, int pass, float lsat, int
   if (w.st[b] != (pass ? ST_PASS2 : ST_PASS1)) return;
   const float lam = (pass || soft) ? w.lam2[(size_t)v * B + b] : c.lam[v];
   const int k0 = c.h_col_ptr[v], k1 = c.h_col_ptr[v + 1];
-  if (lam == __builtin_huge_valf()) {  // cut column: prior probability 0
-    for (int k = k0; k < k1; ++k) w.q[(size_t)c.h_col_edge[k] * B + b] = lsat;
+  if (lam == __builtin_huge_valf()) {  // cut column: prior probability 0 (LLR +inf)
+    for (int k = k0; k < k1; ++k) w.q[(size_t)c.h_col_edge[k] * B + b] = __builtin_huge_valf();
     w.L[(size_t)v * B + b] = lam;
     return;
   }
@@ -280,12 +283,24 @@ __global__ void k_output(DevCode c, PlainWs w, int64_t B, float lsat, uint64_t* 
   }
 }
 
+// The product-sum function phi of bpdc_device.h on an array (accuracy tests).
+__global__ void k_eval_phi(const float* x, int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = bpdc_dev::phi(x[i]);
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t count) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
 }
 
 }  // namespace
+
+hipError_t eval_phi(const float* x, int64_t n, float* out, hipStream_t stream) {
+  (void)hipGetLastError();
+  if (n > 0) hipLaunchKernelGGL(k_eval_phi, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, n, out);
+  return hipGetLastError();
+}
 
 hipError_t fill_u64(uint64_t* p, uint64_t v, size_t count, hipStream_t stream) {
   if (count == 0) return hipSuccess;

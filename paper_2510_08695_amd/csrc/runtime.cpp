@@ -1395,6 +1395,12 @@ bpdc_status bpdc_graph_capture_multi(bpdc_plan p, const int32_t* d_code_of_shot,
   return st;
 }
 
+bpdc_status bpdc_eval_phi(const float* d_x, int64_t n, float* d_out, void* stream) {
+  if (n < 0 || (n > 0 && (!d_x || !d_out))) return fail(BPDC_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(bpdc::eval_phi(d_x, n, d_out, (hipStream_t)stream));
+  return BPDC_OK;
+}
+
 bpdc_status bpdc_graph_launch(bpdc_plan p, void* stream) {
   if (!p) return fail(BPDC_ERR_INVALID_ARG, "null plan");
   if (!p->graph_exec) return fail(BPDC_ERR_INVALID_ARG, "no graph captured on this plan");

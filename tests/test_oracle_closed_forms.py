@@ -12,8 +12,9 @@ oracle documents, never by calling the oracle's own arithmetic:
 * Algorithm 1's second BP run takes the first run's posteriors as its prior
   (Sec. III.A, Sec. III.B for surface-type codes), or the channel prior (BB-type
   codes); the posteriors it takes are the saturated ones DC reads;
-* product-sum (Sec. II.C): r = 2 atanh(prod tanh(|q|/2)), whose magnitude is
-  held at the saturation level when the product rounds to 1;
+* product-sum (Sec. II.C): r = 2 atanh(prod tanh(|q|/2)), in closed form on
+  checks of two and three edges, and held at the saturation level when every
+  other column is frozen (an empty product);
 * DC's random choice among k tied columns is entry floor(h k / 2^64) of the tie
   set in ascending column order, h the 64-bit draw of (seed, shot, row).
 """
@@ -172,32 +173,53 @@ def test_posterior_second_pass_starts_from_saturated_first_pass(precision):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("s0", [0, 1])
-def test_product_sum_magnitude_saturates_when_product_rounds_to_one(precision, s0):
-    """One check on three columns, product-sum, S = 64, prior LLRs (50, 50, 1).
-
-    To column 2: tanh(25) rounds to 1 in both precisions, so the product of the other two
-    is exactly 1, 2 atanh(1) is infinite and the magnitude is held at S: after one
-    iteration L_2 = 1 + S (s = 0, reported saturated as S) or 1 - S = -63 (s = 1).  To
-    column 0: the other product is tanh(25) tanh(1/2) = tanh(1/2), so the magnitude is
-    2 atanh(tanh(1/2)) = 1 up to rounding, and L_0 = 50 -+ 1."""
-    S = 64.0
+def test_product_sum_three_edge_check_closed_form(precision, s0):
+    """One check on three columns, product-sum, one iteration from prior LLRs (a, b, c), all
+    below the saturation level.  The message to the third column is
+    2 atanh(tanh(a/2) tanh(b/2)) = ln(cosh((a+b)/2) / cosh((a-b)/2)) (from
+    tanh x tanh y = (cosh(x+y) - cosh(x-y)) / (cosh(x+y) + cosh(x-y))), signed by the syndrome
+    bit: the posterior is c +- that (saturation far above: nothing is clamped).  Messages up to 60
+    are included, where tanh(|q|/2) rounds to 1 in float64 and a product of tanh values would
+    saturate."""
+    rng = np.random.default_rng(11 + s0)
     H = Csr.from_dense([[1, 1, 1]])
-    lam = np.array([50.0, 50.0, 1.0])
-    s = np.array([s0], np.uint8)
-    _, L, it, _ = oracle.bp_once(H, s, lam, T=1, rule=oracle.PRODUCT_SUM, alpha=1.0, lsat=S,
-                                 precision=precision)
     sign = -1.0 if s0 else 1.0
-    assert it == 1
-    assert L[2] == min(S, 1.0 + sign * S)
-    tol = 1e-6 if precision == "f32" else 1e-12
-    np.testing.assert_allclose(L[:2], 50.0 + sign * 1.0, rtol=tol)
+    tol = 2e-6 if precision == "f32" else 1e-12
+    lams = [rng.uniform(0.05, 60.0, size=3) for _ in range(40)] + [np.array([50.0, 50.0, 1.0]),
+                                                                   np.array([60.0, 45.0, 2.0])]
+    for lam in lams:
+        if precision == "f32":
+            lam = lam.astype(np.float32).astype(np.float64)
+        _, L, it, _ = oracle.bp_once(H, np.array([s0], np.uint8), lam, T=1, rule=oracle.PRODUCT_SUM, alpha=1.0,
+                                     lsat=1e6, precision=precision)
+        assert it == 1
+        for v in range(3):
+            a, b = (lam[u] for u in range(3) if u != v)
+            r = np.log(np.cosh((a + b) / 2) / np.cosh((a - b) / 2))
+            assert abs(L[v] - (lam[v] + sign * r)) <= tol * max(1.0, abs(lam[v] + sign * r)), (lam, v, L[v])
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_product_sum_two_edge_check_passes_the_message_through(precision):
+    """A check of degree 2: 2 atanh(tanh(|q|/2)) = |q|, so each column receives the other's
+    prior LLR exactly (for every magnitude up to the saturation level), signed by the syndrome."""
+    H = Csr.from_dense([[1, 1]])
+    tol = 1e-6 if precision == "f32" else 1e-13
+    for a in (1e-3, 0.1, 1.0, 5.0, 20.0, 40.0, 63.0):
+        for s0 in (0, 1):
+            lam = np.array([a, 2.5])
+            _, L, _, _ = oracle.bp_once(H, np.array([s0], np.uint8), lam, T=1, rule=oracle.PRODUCT_SUM, alpha=1.0,
+                                        lsat=1e6, precision=precision)
+            sign = -1.0 if s0 else 1.0
+            assert abs(L[1] - (2.5 + sign * a)) <= tol * max(1.0, a), (a, s0, L)
+            assert abs(L[0] - (a + sign * 2.5)) <= tol * max(1.0, a), (a, s0, L)
 
 
 def test_product_sum_frozen_columns_send_the_saturation_level():
-    """Algorithm 2 on product-sum: two frozen columns (q = +S, tanh(S/2) = 1) leave the
-    third column a message of magnitude exactly S, as the literal deletion of both columns
-    (Algorithm 1: an empty product, 2 atanh(1)) does; the third column's posterior is
-    lam_2 -+ S."""
+    """Algorithm 2 on product-sum: a frozen column (prior probability 0, LLR +inf) sends
+    tanh(+inf) = 1, so two frozen columns leave the third column the message of an empty
+    product, 2 atanh(1) = +inf, held at the saturation level S, exactly as the literal deletion
+    of both columns (Algorithm 1) does; the third column's posterior is lam_2 -+ S."""
     S = 64.0
     H = Csr.from_dense([[1, 1, 1]])
     lam = np.array([2.0, 3.0, 1.5])
