@@ -70,8 +70,10 @@ struct GArgs {
 
 // Per-check state, one 16-byte record (one LDS access): alpha*min1,
 // alpha*min2, the r-sign bit of every edge of the row and the argmin position.
-// Narrow rows (at most 32 edges): 32 sign bits and the argmin in its own word;
-// wide rows (at most 58): 64 sign bits whose top six hold the argmin.
+// Narrow rows (at most 32 edges): 32 sign bits and, in its own word, the
+// argmin edge as a column-table entry ((check << 10) | position), so that a
+// column compares its entry with it directly; wide rows (at most 58): 64 sign
+// bits whose top six hold the argmin position.
 template <bool Wide>
 struct CheckRec;
 template <>
@@ -80,11 +82,17 @@ struct __align__(16) CheckRec<false> {
   u32 sgn, amin;
   using Word = u32;
   static constexpr Word kSignMask = 0xffffffffu;
-  __device__ __forceinline__ int argmin() const { return (int)amin; }
+  __device__ __forceinline__ int argmin() const { return (int)(amin & 63u); }
   __device__ __forceinline__ Word signs() const { return sgn; }
-  __device__ __forceinline__ u32 sign_bit(int k) const { return (sgn >> k) & 1u; }
-  __device__ __forceinline__ void set(float x1, float x2, Word s, int am) {
-    a1 = x1; a2 = x2; sgn = s; amin = (u32)am;
+  __device__ __forceinline__ void set(float x1, float x2, Word s, int am, int check) {
+    a1 = x1; a2 = x2; sgn = s; amin = ((u32)check << 10) | (u32)am;
+  }
+  // r of the edge with column-table entry `ent` (the magnitude is +0 or
+  // positive, alpha >= 0, or -0 on the dummy check, whose sign bits are 0,
+  // so the sign is or-ed in)
+  __device__ __forceinline__ float r_of(u32 ent) const {
+    const float mag = (amin == ent) ? a2 : a1;
+    return __uint_as_float(__float_as_uint(mag) | (((sgn >> (ent & 31u)) & 1u) << 31));
   }
 };
 template <>
@@ -95,28 +103,73 @@ struct __align__(16) CheckRec<true> {
   static constexpr Word kSignMask = ((u64)1 << 58) - 1u;
   __device__ __forceinline__ int argmin() const { return (int)(hi >> 26); }
   __device__ __forceinline__ Word signs() const { return ((u64)hi << 32) | lo; }
-  __device__ __forceinline__ u32 sign_bit(int k) const { return ((k < 32 ? lo : hi) >> (k & 31)) & 1u; }
-  __device__ __forceinline__ void set(float x1, float x2, Word s, int am) {
+  __device__ __forceinline__ void set(float x1, float x2, Word s, int am, int) {
     a1 = x1; a2 = x2; lo = (u32)s; hi = (u32)(s >> 32) | ((u32)am << 26);
+  }
+  __device__ __forceinline__ float r_of(u32 ent) const {
+    const int k = (int)(ent & 63u);
+    const float mag = (argmin() == k) ? a2 : a1;
+    const u32 bit = ((k < 32 ? lo : hi) >> (k & 31)) & 1u;
+    return __uint_as_float(__float_as_uint(mag) | (bit << 31));
   }
 };
 
 __device__ __forceinline__ int popc_word(u32 x) { return __builtin_popcount(x); }
 __device__ __forceinline__ int popc_word(u64 x) { return __builtin_popcountll(x); }
 
-// r of the edge at row position k: alpha*min2 on the argmin edge, alpha*min1
-// elsewhere, with sign bit k.  The magnitude is +0 or positive (alpha >= 0),
-// or -0 on the dummy check, whose sign bits are 0, so the sign is or-ed in.
-template <bool Wide>
-__device__ __forceinline__ float rec_r(const CheckRec<Wide>& s, int k) {
-  const float mag = (s.argmin() == k) ? s.a2 : s.a1;
-  return __uint_as_float(__float_as_uint(mag) | (s.sign_bit(k) << 31));
-}
-
 // Load through a global-address-space pointer (the code tables are reached
 // through a table in device memory, so the compiler cannot infer it).
-__device__ __forceinline__ int gload(const int32_t* p, int i) {
+__device__ __forceinline__ int gload(const int32_t* p, unsigned i) {
   return ((const __attribute__((address_space(1))) int32_t*)p)[i];
+}
+// The object at LDS address `addr`.  The group kernels use no static LDS, so
+// their dynamic block starts at address 0 (the host checks the static size
+// before the first launch) and an address from the code tables is used as is.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(3))) T* lds_at(u32 addr) {
+  return (const __attribute__((address_space(3))) T*)(uintptr_t)addr;
+}
+
+// A code table as a buffer resource (raw, 32-bit words), so that a load
+// takes its address as a scalar part (the table slice) plus the thread's
+// 32-bit byte offset, with no vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const int32_t* p) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ u32 vtab_at(__amdgpu_buffer_rsrc_t t, u32 scalar_off, u32 byte_off) {
+  return (u32)__builtin_amdgcn_raw_buffer_load_b32(t, byte_off, scalar_off, 0);
+}
+__device__ __forceinline__ float gloadf(const float* p, unsigned i) {
+  return ((const __attribute__((address_space(1))) float*)p)[i];
+}
+
+// A value the whole wave holds (read from LDS or from memory at a uniform
+// address) moved to scalar registers, so that the code description and every
+// address derived from it stay scalar.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uniform(long long x) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long long)x);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  return (T*)uniform((long long)(uintptr_t)p);
+}
+
+// The code description of shot b's code with every field in scalar registers
+// (the compiler loads a struct from memory into vector registers unless it can
+// prove nothing in the kernel writes that memory).
+__device__ __forceinline__ GCode uniform_code(const GCode* codes, int ci) {
+  GCode c = codes[ci];
+  c.n = uniform(c.n); c.m = uniform(c.m); c.md = uniform(c.md);
+  c.h_row_ptr = uniform(c.h_row_ptr); c.h_col = uniform(c.h_col); c.h_col_ptr = uniform(c.h_col_ptr);
+  c.h_col_edge = uniform(c.h_col_edge); c.h_edge_row = uniform(c.h_edge_row);
+  c.d_row_ptr = uniform(c.d_row_ptr); c.d_col = uniform(c.d_col); c.lam = uniform(c.lam);
+  c.v_ell = uniform(c.v_ell); c.c_ell = uniform(c.c_ell); c.v_blk_deg = uniform(c.v_blk_deg);
+  c.max_col_deg = uniform(c.max_col_deg); c.max_row_deg = uniform(c.max_row_deg);
+  return c;
 }
 
 // DC nomination of one row of D (the rule of bpdc_device.h's dc_pick, in the
@@ -156,9 +209,12 @@ __device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg,
 // lane kernels.
 template <bool Wide, bool PS>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_group(GArgs a) {
+  // The kernel's LDS is this one block (no static LDS), so smem is LDS address
+  // 0 and the code tables can hold absolute LDS byte addresses: 16 bytes of
+  // control words, then the shot's state from kLdsHead on.
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ long long sIdx;
-  __shared__ int sUnsat[2];  // stop-test flag, by iteration parity (read and reset with no barrier between)
+  long long& sIdx = *(long long*)smem;
+  int* sUnsat = (int*)(smem + 8);  // stop-test flag, by iteration parity (read and reset with no barrier between)
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const KParams& P = a.p;
@@ -173,21 +229,24 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
   for (;;) {
     if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
     __syncthreads();
-    const long long idx = sIdx;
+    const long long idx = uniform(sIdx);
     __syncthreads();
     if (idx >= nshots) break;
-    const long long b = a.order ? (long long)a.order[idx] : idx;
-    const int ci = a.code_of_shot ? a.code_of_shot[b] : 0;
-    const GCode C = a.codes[ci];
+    const long long b = a.order ? (long long)uniform(a.order[idx]) : idx;
+    const int ci = a.code_of_shot ? uniform(a.code_of_shot[b]) : 0;
+    const GCode C = uniform_code(a.codes, ci);
     const int n = C.n, m = C.m;
     const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
     // LDS carve for this code; check m and column n are the dummies the
     // padding entries of the adjacency tables point at.  Product-sum keeps
     // the r of every edge (CSR order) where min-sum keeps check records.
     const int E = PS ? C.h_row_ptr[m] : 0;
-    Rec* S = (Rec*)smem;                           // [m + 1] check states (min-sum)
-    float* R = (float*)smem;                       // [E] per-edge r (product-sum)
-    float* L = PS ? (float*)(smem + (((size_t)E * 4 + 15) & ~(size_t)15)) : (float*)(S + m + 1);  // [n + 1]
+    unsigned char* state = smem + kLdsHead;
+    const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell);
+    const u32 n4 = (u32)n * 4u, m4 = (u32)m * 4u;
+    Rec* S = (Rec*)state;                          // [m + 1] check states (min-sum)
+    float* R = (float*)state;                      // [E] per-edge r (product-sum)
+    float* L = PS ? (float*)(state + (((size_t)E * 4 + 15) & ~(size_t)15)) : (float*)(S + m + 1);  // [n + 1]
     u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
     u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
     // [n] per-shot prior: the first pass's under soft DC, the second pass's
@@ -204,7 +263,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // new minimum, leaves the second minimum (a median with lsat) and the
     // sign parity unchanged
     if (tid == 0) {
-      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0);
+      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0, m + 1);
       L[n] = INF;
     }
 
@@ -223,7 +282,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       if (PS)
         for (int e = tid; e < E; e += nt) R[e] = 0.0f;
       else
-        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0);
+        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + 1);
       if (pass == 0 && soft)
         for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
       __syncthreads();
@@ -233,7 +292,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         for (int v = tid; v < n; v += nt) {
           float Lv;
           if (use_lam2) Lv = lam2[v];
-          else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : C.lam[v];
+          else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : gloadf(C.lam, v);
           if (PS && Lv != INF) {
             for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
           } else if (Lv != INF) {
@@ -242,17 +301,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             // consecutive columns (v = tid + k nt with nt a multiple of 64), so
             // it can stop at the largest degree of its block (a wave-uniform
             // bound) instead of the code's
-            const int pad = m << 6;
+            const u32 pad = (u32)(m + 1) << 10, vo = (u32)v << 2;
             const int kend = blk_deg ? __builtin_amdgcn_readfirstlane(gload(C.v_blk_deg, v >> 6)) : C.max_col_deg;
             for (int k0 = 0; k0 < kend; k0 += 4) {
-              int ent[4];
+              u32 ent[4];
 #pragma unroll
-              for (int j = 0; j < 4; ++j) ent[j] = (k0 + j < C.max_col_deg) ? gload(C.v_ell, (k0 + j) * n + v) : pad;
+              for (int j = 0; j < 4; ++j)
+                ent[j] = (k0 + j < C.max_col_deg) ? vtab_at(vt, (u32)(k0 + j) * n4, vo) : pad;
               Rec sr[4];
+              // ((check + 1) << 10) >> 6: the LDS address of the check's record
 #pragma unroll
-              for (int j = 0; j < 4; ++j) sr[j] = S[ent[j] >> 6];
+              for (int j = 0; j < 4; ++j) {
+                const u32x4 w = *lds_at<u32x4>(ent[j] >> 6);
+                __builtin_memcpy(&sr[j], &w, sizeof(Rec));
+              }
 #pragma unroll
-              for (int j = 0; j < 4; ++j) Lv = Lv + rec_r<Wide>(sr[j], ent[j] & 63);
+              for (int j = 0; j < 4; ++j) Lv = Lv + sr[j].r_of(ent[j]);
             }
           }
           L[v] = Lv;
@@ -305,24 +369,26 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           float m1 = LS, m2 = LS;
           int amin = 0;
           W sb = 0;
-          // Bit 31 of parw is the parity of the hard decisions [L <= 0]: a
-          // posterior is never -0 (it starts from a prior that is not -0 and
-          // adds messages; x + y is -0 only when both are), so L <= 0 exactly
-          // when bits(L) - 1 has its top bit set (+0 wraps to all ones, +inf
-          // and positive values stay below 2^31).  For the same reason
+          // Bit `lane` of pm is the parity of the hard decisions [L <= 0] of
+          // this check (one wave-wide compare per edge, the xor on the scalar
+          // unit).  A posterior is never -0 (it starts from a prior that is not
+          // -0 and adds messages; x + y is -0 only when both are), so
           // q = sat(L - r) is never -0 and its sign bit is [q < 0].
-          u32 parw = 0u;
+          u64 pm = 0u;
           const int am_old = so.argmin();
+          // the check table holds the LDS address of each entry's L
+          const u32 co = (u32)c << 2, lpad = (u32)((char*)(L + n) - (char*)smem);
           // columns in chunks of 8, all loads of a chunk issued before the
           // updates; padding entries read the dummy column (L = +inf) and
           // change nothing
           for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
-            int vv[8];
+            u32 lo[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) vv[j] = (k0 + j < C.max_row_deg) ? gload(C.c_ell, (k0 + j) * m + c) : n;
+            for (int j = 0; j < 8; ++j)
+              lo[j] = (k0 + j < C.max_row_deg) ? vtab_at(ct, (u32)(k0 + j) * m4, co) : lpad;
             float Lj[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) Lj[j] = L[vv[j]];
+            for (int j = 0; j < 8; ++j) Lj[j] = *lds_at<float>(lo[j]);
             // the old state rebased to this chunk: sign bits at 0..7, argmin - k0
             const u32 ioc = (u32)(io >> k0);
             const int amc = am_old - k0;
@@ -334,7 +400,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
               // row: skipped on a uniform (scalar) branch
               if (k0 + j >= C.max_row_deg) break;
               const float Lv = Lj[j];
-              parw ^= __float_as_uint(Lv) - 1u;
+              pm ^= __ballot(Lv <= 0.0f);
               // r_old: alpha * (min2 on the old argmin, min1 elsewhere) with its
               // sign bit; the magnitude is +0 or positive (alpha >= 0), or -0 on
               // the dummy check, whose sign bits are 0
@@ -351,13 +417,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             amin = (amj >= 0) ? k0 + amj : amin;
             sb |= (W)sbc << k0;
           }
-          const u32 par = (parw >> 31) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
+          const u32 par = ((u32)(pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
           bad |= (int)par;
           const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
           // flip every sign bit on an odd parity: the bits past the row's
           // degree are read only by padding entries, whose q saturates anyway
           const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
-          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin);
+          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + 1);
         }
         if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
         __syncthreads();
@@ -480,7 +546,7 @@ size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edge
   // per-shot prior
   size_t words = (size_t)(n + 1) + ((n + 31) / 32) + ((m + 31) / 32) + (posterior ? n : 0);
   const size_t head = info_bytes == 0 ? (((size_t)edges * 4 + 15) & ~(size_t)15) : (size_t)(m + 1) * 16;
-  return head + words * 4 + 16;
+  return kLdsHead + head + words * 4;
 }
 
 hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_t* code_of_shot,
@@ -542,6 +608,20 @@ int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds) {
     return 0;
   }
   return nb;
+}
+
+bool group_lds_starts_at_zero() {
+  const void* ks[] = {(const void*)k_group<false, false>, (const void*)k_group<true, false>,
+                      (const void*)k_group<false, true>};
+  for (const void* k : ks) {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, k) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (fa.sharedSizeBytes != 0) return false;
+  }
+  return true;
 }
 
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,

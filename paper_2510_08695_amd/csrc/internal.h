@@ -14,6 +14,9 @@ namespace bpdc {
 // degeneracy matrix D in CSR form and the prior LLRs (float, rounded once
 // from double).  Edge e of H is its CSR position; the CSC lists per column
 // the CSR positions of its edges in ascending row order.
+// Bytes of control words at the start of the group kernel's LDS.
+constexpr int kLdsHead = 16;
+
 struct DevCode {
   int n = 0, m = 0, md = 0, E = 0, dnnz = 0;
   int max_row_deg = 0, max_col_deg = 0, max_drow_deg = 0;
@@ -25,8 +28,13 @@ struct DevCode {
   int32_t* d_row_ptr = nullptr;  // [md+1]
   int32_t* d_col = nullptr;      // [dnnz]
   float* lam = nullptr;          // [n]
-  int32_t* v_ell = nullptr;      // [max_col_deg][n] (row << 6 | position in row), ascending rows; pad m << 6
-  int32_t* c_ell = nullptr;      // [max_row_deg][m] column at each row position; pad n
+  // The group kernel's min-sum phases read these two tables as LDS addresses
+  // (its layout: kLdsHead bytes of control words, m + 1 check records of 16
+  // bytes, then L[n + 1]).
+  int32_t* v_ell = nullptr;      // [max_col_deg][n] ((row + kLdsHead / 16) << 10) | position in row, ascending
+                                 // rows: >> 6 is the LDS address of the row's record; pad row m
+  int32_t* c_ell = nullptr;      // [max_row_deg][m] LDS address of L[column] at each row position
+                                 // (kLdsHead + 16 (m + 1) + 4 column); pad column n
   int32_t* v_blk_deg = nullptr;  // [ceil(n/64)] largest column degree of each block of 64 columns
 };
 
@@ -75,6 +83,9 @@ struct GroupTile {
 // the shot's state in dynamic LDS; also the multi-code launch.
 size_t group_lds_bytes_nm(int n, int m, bool posterior, int info_bytes, int edges);
 int group_occupancy(int threads, size_t lds, int info_bytes, int max_lds);
+// True when no group kernel uses static LDS (their dynamic block, and so the
+// LDS addresses in the code tables, start at 0).
+bool group_lds_starts_at_zero();
 // Flags value of a multi-code shot whose code index is outside [0, ncodes): the
 // shot is skipped and nothing else of it is written.
 constexpr uint8_t kFlagBadCode = 0x80;

@@ -923,17 +923,26 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
     }
   }
   std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
-  // padded column-major adjacency for the group kernel (one coalesced load per edge)
-  // padding: check m / column n, dummies that the group kernel keeps in LDS
-  std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, g.m << 6),
-      cell((size_t)std::max(1, d.max_row_deg) * g.m, g.n);
+  // padded column-major adjacency for the group kernel (one coalesced load per
+  // edge), in the forms its min-sum phases use directly: a column's entry is
+  // ((check + 1) << 10) | position in the check's row (>> 6: the LDS address
+  // of the check's 16-byte record, after kLdsHead bytes of control words), a
+  // check's entry the LDS address of the column's posterior, which follows
+  // the m + 1 records.  Padding: check m / column n, dummies that the group
+  // kernel keeps in LDS.  (Codes too large for one workgroup's LDS never run
+  // the group kernel; their entries wrap harmlessly in unsigned arithmetic.)
+  static_assert(bpdc::kLdsHead % 16 == 0, "check records are 16-byte aligned");
+  const uint32_t rec0 = bpdc::kLdsHead / 16, l_off = (uint32_t)bpdc::kLdsHead + ((uint32_t)g.m + 1u) * 16u;
+  std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, (int32_t)(((uint32_t)g.m + rec0) << 10)),
+      cell((size_t)std::max(1, d.max_row_deg) * g.m, (int32_t)(l_off + 4u * (uint32_t)g.n));
   for (int v = 0; v < g.n; ++v)
     for (int k = cp[v]; k < cp[v + 1]; ++k) {
       const int edge = ce[k], r = er[edge];
-      vell[(size_t)(k - cp[v]) * g.n + v] = (r << 6) | (edge - hrp[r]);
+      vell[(size_t)(k - cp[v]) * g.n + v] = (int32_t)((((uint32_t)r + rec0) << 10) | (uint32_t)(edge - hrp[r]));
     }
   for (int r = 0; r < g.m; ++r)
-    for (int k = hrp[r]; k < hrp[r + 1]; ++k) cell[(size_t)(k - hrp[r]) * g.m + r] = hci[k];
+    for (int k = hrp[r]; k < hrp[r + 1]; ++k)
+      cell[(size_t)(k - hrp[r]) * g.m + r] = (int32_t)(l_off + 4u * (uint32_t)hci[k]);
   std::vector<int32_t> vblk((size_t)std::max(1, (g.n + 63) / 64), 0);
   for (int v = 0; v < g.n; ++v) vblk[v >> 6] = std::max(vblk[v >> 6], cp[v + 1] - cp[v]);
   if (hipGetDevice(&c->device) != hipSuccess) return fail(BPDC_ERR_HIP, "no HIP device");
@@ -1052,6 +1061,10 @@ bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_
     void* scratch = nullptr;
     if (bpdc::noalloc_scratch(p->device, &scratch) != hipSuccess) (void)hipGetLastError();
   }
+  // the group kernels read LDS addresses from the code tables, valid only
+  // while their dynamic LDS starts at address 0 (no static LDS)
+  if (!bpdc::group_lds_starts_at_zero())
+    return fail(BPDC_ERR_HIP, "the group kernels were built with static LDS: their code tables do not apply");
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->num_cu = prop.multiProcessorCount;
