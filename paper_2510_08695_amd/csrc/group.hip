@@ -140,6 +140,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const int32_t* p) {
 __device__ __forceinline__ u32 vtab_at(__amdgpu_buffer_rsrc_t t, u32 scalar_off, u32 byte_off) {
   return (u32)__builtin_amdgcn_raw_buffer_load_b32(t, byte_off, scalar_off, 0);
 }
+
+// L + the r of K consecutive slots (from k0) of a column's entries, all loads
+// issued before the sums, in slot (ascending check) order.
+template <int K, class Rec>
+__device__ __forceinline__ float col_sum(float Lv, __amdgpu_buffer_rsrc_t vt, u32 n4, u32 vo, int k0) {
+  u32 ent[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) ent[j] = vtab_at(vt, (u32)(k0 + j) * n4, vo);
+  Rec sr[K];
+  // ((check + 1) << 10) >> 6: the LDS address of the check's record
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const u32x4 w = *lds_at<u32x4>(ent[j] >> 6);
+    __builtin_memcpy(&sr[j], &w, sizeof(Rec));
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) Lv = Lv + sr[j].r_of(ent[j]);
+  return Lv;
+}
 __device__ __forceinline__ float gloadf(const float* p, unsigned i) {
   return ((const __attribute__((address_space(1))) float*)p)[i];
 }
@@ -242,7 +261,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // the r of every edge (CSR order) where min-sum keeps check records.
     const int E = PS ? C.h_row_ptr[m] : 0;
     unsigned char* state = smem + kLdsHead;
-    const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell);
+    const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell),
+                                 lt = table_rsrc((const int32_t*)C.lam);
     const u32 n4 = (u32)n * 4u, m4 = (u32)m * 4u;
     Rec* S = (Rec*)state;                          // [m + 1] check states (min-sum)
     float* R = (float*)state;                      // [E] per-edge r (product-sum)
@@ -289,34 +309,31 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       int t = 0;
       for (;;) {
         // ---- variable phase: L = prior + sum of r (all zero at t = 0) ----
+        // Only the second pass has cut columns (+inf: with the posterior prior
+        // lam2 holds them); the first pass's priors are finite.
+        const bool cuts = pass == 1;
         for (int v = tid; v < n; v += nt) {
+          const u32 vo = (u32)v << 2;
           float Lv;
           if (use_lam2) Lv = lam2[v];
-          else Lv = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : gloadf(C.lam, v);
-          if (PS && Lv != INF) {
+          else if (cuts && ((cutw[v >> 5] >> (v & 31)) & 1u)) Lv = INF;
+          else Lv = __uint_as_float(vtab_at(lt, 0u, vo));
+          if (PS && (!cuts || Lv != INF)) {
             for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
-          } else if (Lv != INF) {
-            // entries in chunks of 4, all loads of a chunk issued before the sums;
-            // padding entries read the dummy check and add -0.  A wave holds 64
-            // consecutive columns (v = tid + k nt with nt a multiple of 64), so
-            // it can stop at the largest degree of its block (a wave-uniform
-            // bound) instead of the code's
-            const u32 pad = (u32)(m + 1) << 10, vo = (u32)v << 2;
+          } else if (!PS && (!cuts || Lv != INF)) {
+            // entries in chunks of 4 and a last chunk of kend mod 4; padding
+            // entries of columns shorter than kend read the dummy check and add
+            // -0 (x + -0 = x).  A wave holds 64 consecutive columns (v = tid +
+            // k nt with nt a multiple of 64), so it can stop at the largest
+            // degree of its block (a wave-uniform bound) instead of the code's
             const int kend = blk_deg ? __builtin_amdgcn_readfirstlane(gload(C.v_blk_deg, v >> 6)) : C.max_col_deg;
-            for (int k0 = 0; k0 < kend; k0 += 4) {
-              u32 ent[4];
-#pragma unroll
-              for (int j = 0; j < 4; ++j)
-                ent[j] = (k0 + j < C.max_col_deg) ? vtab_at(vt, (u32)(k0 + j) * n4, vo) : pad;
-              Rec sr[4];
-              // ((check + 1) << 10) >> 6: the LDS address of the check's record
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const u32x4 w = *lds_at<u32x4>(ent[j] >> 6);
-                __builtin_memcpy(&sr[j], &w, sizeof(Rec));
-              }
-#pragma unroll
-              for (int j = 0; j < 4; ++j) Lv = Lv + sr[j].r_of(ent[j]);
+            int k0 = 0;
+            for (; k0 + 4 <= kend; k0 += 4) Lv = col_sum<4, Rec>(Lv, vt, n4, vo, k0);
+            switch (kend - k0) {  // uniform
+              case 1: Lv = col_sum<1, Rec>(Lv, vt, n4, vo, k0); break;
+              case 2: Lv = col_sum<2, Rec>(Lv, vt, n4, vo, k0); break;
+              case 3: Lv = col_sum<3, Rec>(Lv, vt, n4, vo, k0); break;
+              default: break;
             }
           }
           L[v] = Lv;
