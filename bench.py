@@ -415,6 +415,7 @@ def _single(args, code, B, seed, prm, workload, metric, kernel, traffic_key=None
            "ms_per_step": ms, "dtype": "f32", "data": "synthetic", "config": {"workload": workload,
            "shots_per_step": B, "plan": plan.info(0)},
            "ler": ler, "ler_ci95": ci, "dc_rate": n_dc / B, "mean_iters": float(iters.sum()) / B,
+           "autotune": plan.describe(0),
            "roofline": {"bound": "alu", "achieved": ops / (ms / 1e3) / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                         "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
                         "traffic": committed_traffic(traffic_key) if traffic_key else None,

@@ -70,10 +70,14 @@ struct GArgs {
 
 // Per-check state, one 16-byte record (one LDS access): alpha*min1,
 // alpha*min2, the r-sign bit of every edge of the row and the argmin position.
-// Narrow rows (at most 32 edges): 32 sign bits and, in its own word, the
-// argmin edge as a column-table entry ((check << 10) | position), so that a
-// column compares its entry with it directly; wide rows (at most 58): 64 sign
-// bits whose top six hold the argmin position.
+// Narrow rows (at most 32 edges): 32 sign bits, row position k at bit 31 - k
+// (the check phase shifts each q's sign in from the bottom), and, in its own
+// word, the argmin edge as a column-table entry ((check << 10) | position), so
+// that a column compares its entry with it directly; wide rows (at most 58):
+// 64 sign bits, position k at bit k, whose top six hold the argmin position.
+// old_sign: the sign bit of position k of a sign word, at bit 31;
+// push_sign / finish_signs: the sign word of q over positions 0 .. K-1 built
+// one position at a time.
 template <bool Wide>
 struct CheckRec;
 template <>
@@ -92,8 +96,13 @@ struct __align__(16) CheckRec<false> {
   // so the sign is or-ed in)
   __device__ __forceinline__ float r_of(u32 ent) const {
     const float mag = (amin == ent) ? a2 : a1;
-    return __uint_as_float(__float_as_uint(mag) | (((sgn >> (ent & 31u)) & 1u) << 31));
+    return __uint_as_float(__float_as_uint(mag) | ((sgn << (ent & 31u)) & 0x80000000u));
   }
+  static __device__ __forceinline__ u32 old_sign(Word io, int k) { return (io << k) & 0x80000000u; }
+  static __device__ __forceinline__ Word push_sign(Word sb, float q, int) {
+    return __builtin_amdgcn_alignbit(sb, __float_as_uint(q), 31);  // (sb << 1) | sign(q)
+  }
+  static __device__ __forceinline__ Word finish_signs(Word sb, int K) { return K > 0 ? sb << (32 - K) : 0u; }
 };
 template <>
 struct __align__(16) CheckRec<true> {
@@ -112,6 +121,11 @@ struct __align__(16) CheckRec<true> {
     const u32 bit = ((k < 32 ? lo : hi) >> (k & 31)) & 1u;
     return __uint_as_float(__float_as_uint(mag) | (bit << 31));
   }
+  static __device__ __forceinline__ u32 old_sign(Word io, int k) { return ((u32)(io >> k) & 1u) << 31; }
+  static __device__ __forceinline__ Word push_sign(Word sb, float q, int k) {
+    return sb | ((Word)(__float_as_uint(q) >> 31) << k);
+  }
+  static __device__ __forceinline__ Word finish_signs(Word sb, int) { return sb; }
 };
 
 __device__ __forceinline__ int popc_word(u32 x) { return __builtin_popcount(x); }
@@ -138,7 +152,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const int32_t* p) {
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, 0x7fffffff, 0x00020000);
 }
 __device__ __forceinline__ u32 vtab_at(__amdgpu_buffer_rsrc_t t, u32 scalar_off, u32 byte_off) {
-  return (u32)__builtin_amdgcn_raw_buffer_load_b32(t, byte_off, scalar_off, 0);
+  // (readfirstlane: the offset is uniform; it keeps the compiler from a
+  // per-value loop where register pressure has moved it to a vector register)
+  return (u32)__builtin_amdgcn_raw_buffer_load_b32(t, byte_off, __builtin_amdgcn_readfirstlane(scalar_off), 0);
 }
 
 // L + the r of K consecutive slots (from k0) of a column's entries, all loads
@@ -158,6 +174,75 @@ __device__ __forceinline__ float col_sum(float Lv, __amdgpu_buffer_rsrc_t vt, u3
 #pragma unroll
   for (int j = 0; j < K; ++j) Lv = Lv + sr[j].r_of(ent[j]);
   return Lv;
+}
+
+// The first K table entries of a column and its prior (K uniform, at most 4).
+__device__ __forceinline__ void col_fetch(u32 (&e)[4], float& lam, int K, __amdgpu_buffer_rsrc_t vt,
+                                          __amdgpu_buffer_rsrc_t lt, u32 n4, u32 vo) {
+  lam = __uint_as_float(vtab_at(lt, 0u, vo));
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j < K) e[j] = vtab_at(vt, (u32)j * n4, vo);
+}
+
+// L + the r of a column's K fetched entries, in slot (ascending check) order.
+template <int K, class Rec>
+__device__ __forceinline__ float col_add(float Lv, const u32 (&e)[4]) {
+  Rec sr[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const u32x4 w = *lds_at<u32x4>(e[j] >> 6);
+    __builtin_memcpy(&sr[j], &w, sizeof(Rec));
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) Lv = Lv + sr[j].r_of(e[j]);
+  return Lv;
+}
+
+// Running state of a check over its row: min1, min2 and argmin of |q|, the
+// sign word of q, and (bit `lane`) the parity of the hard decisions [L <= 0].
+template <class Rec>
+struct RowAcc {
+  float m1, m2;
+  int amin;
+  typename Rec::Word sb;
+  u64 pm;
+};
+
+// K consecutive row slots (from k0) of a check: q = sat(L - r_old) in row
+// order, all loads issued before the updates.  r_old is alpha * (min2 on the
+// old argmin, min1 elsewhere) with its sign bit (the magnitude is +0 or
+// positive, alpha >= 0, or -0 on the dummy check, whose sign bits are 0).  A
+// posterior is never -0 (it starts from a prior that is not -0 and adds
+// messages; x + y is -0 only when both are), so q is never -0 and its sign bit
+// is [q < 0]; the hard-decision parity takes one wave-wide compare per edge,
+// the xor on the scalar unit.
+template <int K, class Rec>
+__device__ __forceinline__ void row_chunk(RowAcc<Rec>& a, const Rec& so, typename Rec::Word io, int am_old, int k0,
+                                          __amdgpu_buffer_rsrc_t ct, u32 m4, u32 co, float LS) {
+  u32 lo[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) lo[j] = vtab_at(ct, (u32)(k0 + j) * m4, co);
+  float Lj[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) Lj[j] = *lds_at<float>(lo[j]);
+  int amj = -1;  // position in the chunk of the newest minimum, if any (a constant per slot)
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int k = k0 + j;
+    const float Lv = Lj[j];
+    a.pm ^= __ballot(Lv <= 0.0f);
+    const float mag = (am_old == k) ? so.a2 : so.a1;
+    const float r = __uint_as_float(Rec::old_sign(io, k) | __float_as_uint(mag));
+    const float q = bpdc_dev::sat(Lv - r, LS);
+    const float aq = fabsf(q);
+    const bool lt = aq < a.m1;
+    amj = lt ? j : amj;
+    a.m2 = __builtin_amdgcn_fmed3f(aq, a.m1, a.m2);
+    a.m1 = lt ? aq : a.m1;
+    a.sb = Rec::push_sign(a.sb, q, k);
+  }
+  a.amin = (amj >= 0) ? k0 + amj : a.amin;
 }
 __device__ __forceinline__ float gloadf(const float* p, unsigned i) {
   return ((const __attribute__((address_space(1))) float*)p)[i];
@@ -312,6 +397,29 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         // Only the second pass has cut columns (+inf: with the posterior prior
         // lam2 holds them); the first pass's priors are finite.
         const bool cuts = pass == 1;
+        if (!PS && !use_lam2 && !cuts && !blk_deg && C.max_col_deg <= 4) {
+          // first pass (no cut columns, the channel prior), columns of at most
+          // 4 entries: software-pipelined, the next column's table entries and
+          // prior are in flight while this column's check records are read
+          // and summed (the same sums in the same order)
+          const int K = C.max_col_deg;
+          u32 e[4] = {0u, 0u, 0u, 0u};
+          float lam = 0.0f;
+          if (tid < n) col_fetch(e, lam, K, vt, lt, n4, (u32)tid << 2);
+          for (int v = tid; v < n; v += nt) {
+            const u32 ce[4] = {e[0], e[1], e[2], e[3]};
+            float Lv = lam;
+            if (v + nt < n) col_fetch(e, lam, K, vt, lt, n4, (u32)(v + nt) << 2);
+            switch (K) {  // uniform
+              case 4: Lv = col_add<4, Rec>(Lv, ce); break;
+              case 3: Lv = col_add<3, Rec>(Lv, ce); break;
+              case 2: Lv = col_add<2, Rec>(Lv, ce); break;
+              case 1: Lv = col_add<1, Rec>(Lv, ce); break;
+              default: break;
+            }
+            L[v] = Lv;
+          }
+        } else
         for (int v = tid; v < n; v += nt) {
           const u32 vo = (u32)v << 2;
           float Lv;
@@ -382,59 +490,23 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         } else
         for (int c = tid; c < m; c += nt) {
           const Rec so = S[c];
+          RowAcc<Rec> acc{LS, LS, 0, 0, 0u};
+          // the check table holds the LDS address of each entry's L; the
+          // code's largest row degree in chunks of 8, then 4, 2, 1 (uniform
+          // branches; padding entries of shorter rows read the dummy column,
+          // L = +inf, whose q saturates and changes nothing)
+          const u32 co = (u32)c << 2;
           const W io = so.signs();
-          float m1 = LS, m2 = LS;
-          int amin = 0;
-          W sb = 0;
-          // Bit `lane` of pm is the parity of the hard decisions [L <= 0] of
-          // this check (one wave-wide compare per edge, the xor on the scalar
-          // unit).  A posterior is never -0 (it starts from a prior that is not
-          // -0 and adds messages; x + y is -0 only when both are), so
-          // q = sat(L - r) is never -0 and its sign bit is [q < 0].
-          u64 pm = 0u;
-          const int am_old = so.argmin();
-          // the check table holds the LDS address of each entry's L
-          const u32 co = (u32)c << 2, lpad = (u32)((char*)(L + n) - (char*)smem);
-          // columns in chunks of 8, all loads of a chunk issued before the
-          // updates; padding entries read the dummy column (L = +inf) and
-          // change nothing
-          for (int k0 = 0; k0 < C.max_row_deg; k0 += 8) {
-            u32 lo[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-              lo[j] = (k0 + j < C.max_row_deg) ? vtab_at(ct, (u32)(k0 + j) * m4, co) : lpad;
-            float Lj[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) Lj[j] = *lds_at<float>(lo[j]);
-            // the old state rebased to this chunk: sign bits at 0..7, argmin - k0
-            const u32 ioc = (u32)(io >> k0);
-            const int amc = am_old - k0;
-            int amj = -1;  // position in the chunk of the newest minimum, if any
-            u32 sbc = 0u;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              // slots past the code's largest row degree hold padding in every
-              // row: skipped on a uniform (scalar) branch
-              if (k0 + j >= C.max_row_deg) break;
-              const float Lv = Lj[j];
-              pm ^= __ballot(Lv <= 0.0f);
-              // r_old: alpha * (min2 on the old argmin, min1 elsewhere) with its
-              // sign bit; the magnitude is +0 or positive (alpha >= 0), or -0 on
-              // the dummy check, whose sign bits are 0
-              const float mag = (amc == j) ? so.a2 : so.a1;
-              const float r = __uint_as_float(((ioc << (31 - j)) & 0x80000000u) | __float_as_uint(mag));
-              const float q = bpdc_dev::sat(Lv - r, LS);
-              const float aq = fabsf(q);
-              const bool lt = aq < m1;
-              amj = lt ? j : amj;
-              m2 = __builtin_amdgcn_fmed3f(aq, m1, m2);
-              m1 = lt ? aq : m1;
-              sbc |= (__float_as_uint(q) >> 31) << j;
-            }
-            amin = (amj >= 0) ? k0 + amj : amin;
-            sb |= (W)sbc << k0;
-          }
-          const u32 par = ((u32)(pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
+          const int am_old = so.argmin(), K = C.max_row_deg;
+          int k0 = 0;
+          for (; k0 + 8 <= K; k0 += 8) row_chunk<8, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
+          if ((K - k0) & 4) { row_chunk<4, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 4; }
+          if ((K - k0) & 2) { row_chunk<2, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 2; }
+          if ((K - k0) & 1) row_chunk<1, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
+          const W sb = Rec::finish_signs(acc.sb, K);
+          const float m1 = acc.m1, m2 = acc.m2;
+          const int amin = acc.amin;
+          const u32 par = ((u32)(acc.pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
           bad |= (int)par;
           const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
           // flip every sign bit on an odd parity: the bits past the row's

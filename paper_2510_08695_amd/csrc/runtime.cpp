@@ -512,12 +512,23 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   bpdc::GroupTile base;
   base.info_bytes = group_variant(p, d);
   base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes, d.E);
+  // powers of two, and the multiples of 64 that split the columns or the
+  // checks into whole rounds of one item per thread (the last round of each
+  // phase is otherwise partly idle at the phase's barrier)
   std::vector<int> cands;
-  for (int t : {64, 128, 256, 512, 1024}) {
-    const int work = std::max(d.n, d.m);
-    if (t > 64 && t / 2 >= work) continue;  // more threads than items
-    cands.push_back(t);
-  }
+  const int work = std::max(d.n, d.m);
+  auto add = [&](int t) {
+    if (t < 64 || t > 1024 || (t > 64 && t / 2 >= work)) return;  // more threads than items
+    if (std::find(cands.begin(), cands.end(), t) == cands.end()) cands.push_back(t);
+  };
+  for (int t : {64, 128, 256, 512, 1024}) add(t);
+  for (int w : {d.n, d.m})
+    for (int r = 1; r <= 12; ++r) {
+      const int t = 64 * ((w + 64 * r - 1) / (64 * r));
+      if (t >= 256) add(t);
+    }
+  if (const char* e = getenv("BPDC_GROUP_THREADS"))  // pins the threads per workgroup
+    cands = {std::min(1024, std::max(64, atoi(e) / 64 * 64))};
   auto make = [&](int threads) {
     bpdc::GroupTile t = base;
     t.threads = threads;
@@ -532,7 +543,9 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
     if (best_ms_out) *best_ms_out = -1.0f;
     return BPDC_OK;
   }
-  const int S = (int)std::max<int64_t>(64, std::min<int64_t>(4096, (1 << 21) / std::max(1, d.E)));
+  // enough shots to fill every workgroup slot twice (throughput, not the
+  // latency of a few shots), more for small codes
+  const int S = (int)std::max<int64_t>(4 * p->num_cu, std::min<int64_t>(4096, (1 << 21) / std::max(1, d.E)));
   TuneBuffers tb;
   const int sw = (d.m + 63) / 64, nw = (d.n + 63) / 64;
   std::vector<uint64_t> hs = autotune_syndromes(p->codes[code], S, 0x5EED0000ull + (uint64_t)code);
