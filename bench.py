@@ -343,18 +343,24 @@ def _dc_diagnostics(plan, syn, n, steps, stream, paper_flat=None):
     s = st.cpu().numpy()
     ms = _timed(lambda: plan.decode(syn), steps, stream)
     plan.set_dc_stats(None)
-    spread, n_dc, cuts = s[:101], int(s[101]), s[102:]
-    sizes = np.arange(cuts.size)
-    nz = np.nonzero(cuts)[0]
-    res = {"dc_shots": n_dc, "rows": int(spread.sum()),
-           "flat_fraction": {str(e): float(spread[:round(100 * e)].sum() / max(1, spread.sum()))
-                             for e in (0.1, 0.2, 0.3, 0.4, 0.5)},
-           "mean_cut": float((sizes * cuts).sum() / max(1, n_dc)),
-           "cut_range": [int(nz[0]), int(nz[-1])] if nz.size else None,
-           "ms_per_step_with_diagnostics": ms}
+    res = _dc_summary(s)
+    res["ms_per_step_with_diagnostics"] = ms
     if paper_flat:
         res["flat_fraction_paper"] = paper_flat
     return res
+
+
+def _dc_summary(s):
+    """Flatness fractions (Table IV's statistic), DC shots and cut sizes from a DC
+    diagnostics buffer."""
+    spread, n_dc, cuts = s[:101], int(s[101]), s[102:]
+    sizes = np.arange(cuts.size)
+    nz = np.nonzero(cuts)[0]
+    return {"dc_shots": n_dc, "rows": int(spread.sum()),
+            "flat_fraction": {str(e): float(spread[:round(100 * e)].sum() / max(1, spread.sum()))
+                              for e in (0.1, 0.2, 0.3, 0.4, 0.5)},
+            "mean_cut": float((sizes * cuts).sum() / max(1, n_dc)),
+            "cut_range": [int(nz[0]), int(nz[-1])] if nz.size else None}
 
 
 def _oracle_sample(code, syndromes, errors, op, seconds, chunk=2000):
@@ -487,7 +493,7 @@ def run_circuit(args):
     B = 20_000
     res = _single(args, code, B, 2012, prm, f"BB[[144,12,12]] circuit-level p=0.001, T=12 rounds (DCM 936x8784, "
                   f"w=3 DDM 9576 rows), {B} shots, alpha=0.625, T=1000+1000", "shots/s BP+DC circuit-level BB144",
-                  P.KERNEL_GROUP, traffic_key="circuit", cpu_chunk=100)
+                  P.KERNEL_GROUP, traffic_key="circuit", cpu_chunk=100, paper_flat={})
     print(json.dumps(res), flush=True)
 
 
@@ -549,7 +555,7 @@ def run_phen(args):
     res = _single(args, code, B, 3, prm, f"BB[[288,12,18]] phenomenological T=18 p=0.003 ({args.dem_form} "
                   f"time boundary, {code.H.rows}x{code.n}), {B} shots, alpha=0.625, T=1000+1000",
                   "shots/s BP+DC phenomenological BB288 T=18", P.KERNEL_GROUP,
-                  traffic_key="phen" if (B == 100_000 and not final) else None)
+                  traffic_key="phen" if (B == 100_000 and not final) else None, paper_flat={})
     print(json.dumps(res), flush=True)
 
 
@@ -602,6 +608,14 @@ def run_hgp64(args):
                         "unit": "Tlane-op/s", "frac": ops / (ms / 1e3) / PEAK_LANE_OPS,
                         "traffic": committed_traffic("hgp64"), "traffic_unit": "bytes per launch",
                         "launch_ms": ms, "ops_per_launch": ops}}
+    if not args.no_diag:
+        # DC diagnostics of the whole mixed batch (one untimed eager multi-code launch)
+        st = torch.zeros(103 + max(c.n for c in codes), dtype=torch.int64, device="cuda")
+        plan.set_dc_stats(st)
+        plan.decode_multi(cos, syn, so, corr, co, flags, iters)
+        torch.cuda.synchronize()
+        plan.set_dc_stats(None)
+        res["dc_diagnostics"] = _dc_summary(st.cpu().numpy())
     if not args.no_cpu:
         # the float64 oracle on the first shots of every code, for about --cpu-seconds in total
         cores = len(os.sched_getaffinity(0))

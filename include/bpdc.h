@@ -176,9 +176,10 @@ bpdc_status bpdc_plan_describe(bpdc_plan plan, int32_t code, char* buf, size_t c
  *                floor(100 Delta) (bin 100: Delta = 1);
  *   [101]        number of shots that ran DC;
  *   [102, 103+n) histogram of the cut size 0..n.
- * words >= 103 + n of the decoded code (checked at decode time).  d_stats =
- * NULL turns it off.  Lane and plain kernel families; decodes on the group
- * family or the multi-code launch return BPDC_ERR_UNSUPPORTED while set. */
+ * words >= 103 + n of the decoded code (bpdc_decode_multi: of the plan's
+ * largest code; checked at decode time).  d_stats = NULL turns it off.  Every
+ * kernel family and bpdc_decode_multi; bpdc_graph_capture_multi returns
+ * BPDC_ERR_UNSUPPORTED while set (a captured graph would keep the buffer). */
 bpdc_status bpdc_plan_set_dc_stats(bpdc_plan plan, uint64_t* d_stats, int64_t words);
 
 /* Device workspace (bytes) that bpdc_decode needs for a batch of B shots of

@@ -79,6 +79,16 @@ __device__ __forceinline__ int dc_pick(const int* cols, const float* vals, int d
 // error probabilities p = 1 / (1 + e^L) over a row of D (largest minus
 // smallest; p falls as L grows, so it is p(min L) - p(max L)), as a bin
 // floor(100 spread) in 0..100.  e^L by the hardware exp2 (about 1 ulp).
+// spread_bin_of takes the row's smallest and largest saturated posterior,
+// spread_bin the row's values.
+__device__ __forceinline__ int spread_bin_of(float lo, float hi) {
+  const float lg = 1.44269504088896341f;
+  const float plo = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(lo * lg));
+  const float phi = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(hi * lg));
+  const int bin = (int)((plo - phi) * 100.0f);
+  return bin < 0 ? 0 : (bin > 100 ? 100 : bin);
+}
+
 template <int MAXD>
 __device__ __forceinline__ int spread_bin(const float* vals, int deg) {
   float lo = vals[0], hi = vals[0];
@@ -87,11 +97,7 @@ __device__ __forceinline__ int spread_bin(const float* vals, int deg) {
       lo = fminf(lo, vals[k]);
       hi = fmaxf(hi, vals[k]);
     }
-  const float lg = 1.44269504088896341f;
-  const float plo = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(lo * lg));
-  const float phi = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(hi * lg));
-  const int bin = (int)((plo - phi) * 100.0f);
-  return bin < 0 ? 0 : (bin > 100 ? 100 : bin);
+  return spread_bin_of(lo, hi);
 }
 
 // Product-sum rule (Sec. II.C) in the log domain: with

@@ -49,6 +49,11 @@ namespace {
 using bpdc_dev::u32;
 using bpdc_dev::u64;
 
+// Check c's record sits at LDS address 16 (c + kRec0) (after the control
+// words); the column-table entries and the narrow records' argmin name it as
+// ((c + kRec0) << 10) | position.
+constexpr int kRec0 = kLdsHead / 16;
+
 struct GArgs {
   const GCode* codes;
   const int32_t* code_of_shot;  // null: every shot is code 0
@@ -65,6 +70,7 @@ struct GArgs {
   int64_t shot_offset;
   unsigned long long* queue;
   const unsigned* n_bad;        // multi-code: shots with an out-of-range code index (kept out of `order`)
+  unsigned long long* dcstats;  // DC diagnostics (spread bins, DC shots, cut sizes) or null
   KParams p;
 };
 
@@ -72,7 +78,7 @@ struct GArgs {
 // alpha*min2, the r-sign bit of every edge of the row and the argmin position.
 // Narrow rows (at most 32 edges): 32 sign bits, row position k at bit 31 - k
 // (the check phase shifts each q's sign in from the bottom), and, in its own
-// word, the argmin edge as a column-table entry ((check << 10) | position), so
+// word, the argmin edge as a column-table entry (((check + kRec0) << 10) | position), so
 // that a column compares its entry with it directly; wide rows (at most 58):
 // 64 sign bits, position k at bit k, whose top six hold the argmin position.
 // old_sign: the sign bit of position k of a sign word, at bit 31;
@@ -165,7 +171,7 @@ __device__ __forceinline__ float col_sum(float Lv, __amdgpu_buffer_rsrc_t vt, u3
 #pragma unroll
   for (int j = 0; j < K; ++j) ent[j] = vtab_at(vt, (u32)(k0 + j) * n4, vo);
   Rec sr[K];
-  // ((check + 1) << 10) >> 6: the LDS address of the check's record
+  // ((check + kRec0) << 10) >> 6: the LDS address of the check's record
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const u32x4 w = *lds_at<u32x4>(ent[j] >> 6);
@@ -282,9 +288,15 @@ __device__ __forceinline__ GCode uniform_code(const GCode* codes, int ci) {
 // saturated posteriors, the tie threshold, the number of ties, then the
 // chosen tie in ascending column order.
 __device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg, const float* L, float lsat,
-                                           float tie_eps, int tie_lowest, u64 seed, u64 shot, u64 row) {
-  float lmax = bpdc_dev::sat(L[gload(dcol, e0)], lsat);
-  for (int k = 1; k < deg; ++k) lmax = fmaxf(lmax, bpdc_dev::sat(L[gload(dcol, e0 + k)], lsat));
+                                           float tie_eps, int tie_lowest, u64 seed, u64 shot, u64 row,
+                                           int* spread = nullptr) {
+  float lmax = bpdc_dev::sat(L[gload(dcol, e0)], lsat), lmin = lmax;
+  for (int k = 1; k < deg; ++k) {
+    const float x = bpdc_dev::sat(L[gload(dcol, e0 + k)], lsat);
+    lmax = fmaxf(lmax, x);
+    lmin = fminf(lmin, x);
+  }
+  if (spread) *spread = bpdc_dev::spread_bin_of(lmin, lmax);  // DC diagnostics (Appendix B)
   const float scale = fmaxf(1.0f, fabsf(lmax));
   const float thr = lmax - tie_eps * scale;
   int nt = 0;
@@ -319,6 +331,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
   extern __shared__ __align__(16) unsigned char smem[];
   long long& sIdx = *(long long*)smem;
   int* sUnsat = (int*)(smem + 8);  // stop-test flag, by iteration parity (read and reset with no barrier between)
+  unsigned& sCount = *(unsigned*)(smem + 16);  // DC diagnostics: the shot's cut size
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
   const KParams& P = a.p;
@@ -368,7 +381,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     // new minimum, leaves the second minimum (a median with lsat) and the
     // sign parity unchanged
     if (tid == 0) {
-      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0, m + 1);
+      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0, m + kRec0);
       L[n] = INF;
     }
 
@@ -387,7 +400,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       if (PS)
         for (int e = tid; e < E; e += nt) R[e] = 0.0f;
       else
-        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + 1);
+        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + kRec0);
       if (pass == 0 && soft)
         for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
       __syncthreads();
@@ -512,7 +525,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           // flip every sign bit on an odd parity: the bits past the row's
           // degree are read only by padding entries, whose q saturates anyway
           const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
-          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + 1);
+          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + kRec0);
         }
         if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
         __syncthreads();
@@ -548,18 +561,47 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       }
       if (pass == 1 || conv) break;
       // ---- degeneracy cutting (first pass failed) ----
+      // With diagnostics on, each row's spread bin goes to a histogram of the
+      // shot in LDS over the check-state region (free between the passes),
+      // flushed once per shot; a code whose region holds fewer than 101 bins
+      // adds to the device histogram directly.
+      const bool dcs = a.dcstats != nullptr;
+      u32* hist = (u32*)state;
+      const bool lds_hist = dcs && (PS ? (size_t)E * 4 : (size_t)(m + 1) * 16) >= 101 * sizeof(u32);
+      if (lds_hist) {
+        for (int i = tid; i < 101; i += nt) hist[i] = 0u;
+        if (tid == 0) sCount = 0u;
+        __syncthreads();
+      } else if (dcs && tid == 0) {
+        sCount = 0u;  // ordered before its use by the barrier after the rows
+      }
       for (int h = tid; h < C.md; h += nt) {
         const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
         if (deg == 0) continue;
+        int bin = 0;
         const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
-                                     (u64)(a.shot_offset + b), (u64)h);
+                                     (u64)(a.shot_offset + b), (u64)h, dcs ? &bin : nullptr);
         atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+        if (lds_hist) atomicAdd(&hist[bin], 1u);
+        else if (dcs) atomicAdd(&a.dcstats[bin], 1ull);
       }
       __syncthreads();
+      if (dcs) {
+        if (lds_hist)
+          for (int i = tid; i < 101; i += nt)
+            if (hist[i]) atomicAdd(&a.dcstats[i], (unsigned long long)hist[i]);
+        unsigned nc = 0;
+        for (int w = tid; w < ((n + 31) >> 5); w += nt) nc += (unsigned)__builtin_popcount(cutw[w]);
+        if (nc) atomicAdd(&sCount, nc);
+      }
       if (P.second_pass_posterior)
         for (int v = tid; v < n; v += nt)
           lam2[v] = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : bpdc_dev::sat(L[v], LS);
       __syncthreads();
+      if (dcs && tid == 0) {  // the shot ran DC; its cut size
+        atomicAdd(&a.dcstats[101], 1ull);
+        atomicAdd(&a.dcstats[102 + sCount], 1ull);
+      }
     }
     // ---- outputs ----
     const bool dc = it[1] > 0;
@@ -642,8 +684,10 @@ hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_
                         const int32_t* order, const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
-                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream) {
+                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream,
+                        unsigned long long* dcstats) {
   GArgs a;
+  a.dcstats = dcstats;
   a.codes = (const GCode*)d_codes;
   a.code_of_shot = code_of_shot;
   a.n_bad = n_bad;

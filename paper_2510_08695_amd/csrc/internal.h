@@ -15,7 +15,7 @@ namespace bpdc {
 // from double).  Edge e of H is its CSR position; the CSC lists per column
 // the CSR positions of its edges in ascending row order.
 // Bytes of control words at the start of the group kernel's LDS.
-constexpr int kLdsHead = 16;
+constexpr int kLdsHead = 32;
 
 struct DevCode {
   int n = 0, m = 0, md = 0, E = 0, dnnz = 0;
@@ -95,7 +95,8 @@ hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_
                         const int32_t* order, const KParams& p, const uint64_t* syn, const int64_t* syn_off, uint64_t* corr,
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
-                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream);
+                        size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream,
+                        unsigned long long* dcstats = nullptr);
 // hist and base hold ncodes + 1 entries each; hist[ncodes] counts the shots with an
 // out-of-range code index, which get flags kFlagBadCode and no place in `order`.
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,

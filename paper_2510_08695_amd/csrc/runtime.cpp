@@ -743,7 +743,8 @@ size_t multi_ws_bytes(const bpdc_plan_s* p, int64_t B) {
 
 bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* syn, const int64_t* syn_off,
                           uint64_t* corr, const int64_t* corr_off, uint8_t* flags, int16_t* iters, int64_t B,
-                          int64_t shot_offset, void* ws, hipStream_t s, const bpdc::GroupTile* tile = nullptr) {
+                          int64_t shot_offset, void* ws, hipStream_t s, const bpdc::GroupTile* tile = nullptr,
+                          unsigned long long* dcstats = nullptr) {
   const bpdc::GroupTile& t = tile ? *tile : p->multi_tile;
   char* w = (char*)ws;
   unsigned long long* queue = (unsigned long long*)w;
@@ -752,7 +753,8 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
   int32_t* order = (int32_t*)(w + 256 + 2 * align256((p->codes.size() + 1) * 4));
   HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, flags, s));
   HIP_TRY(bpdc::group_launch(p->d_code_table, hist + p->codes.size(), cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
-                             nullptr, iters, B, shot_offset, t.threads, t.grid, t.lds_bytes, t.info_bytes, queue, s));
+                             nullptr, iters, B, shot_offset, t.threads, t.grid, t.lds_bytes, t.info_bytes, queue, s,
+                             dcstats));
   return BPDC_OK;
 }
 
@@ -938,7 +940,7 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
   std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
   // padded column-major adjacency for the group kernel (one coalesced load per
   // edge), in the forms its min-sum phases use directly: a column's entry is
-  // ((check + 1) << 10) | position in the check's row (>> 6: the LDS address
+  // ((check + kLdsHead / 16) << 10) | position in the check's row (>> 6: the LDS address
   // of the check's 16-byte record, after kLdsHead bytes of control words), a
   // check's entry the LDS address of the column's posterior, which follows
   // the m + 1 records.  Padding: check m / column n, dummies that the group
@@ -1306,8 +1308,6 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
   const CodePlan& cp = p->per_code[code];
   bpdc_code c = p->codes[code];
   if (p->dcstats) {
-    if (cp.kernel == BPDC_KERNEL_GROUP)
-      return fail(BPDC_ERR_UNSUPPORTED, "DC diagnostics are kept by the lane and plain kernel families only");
     if (p->dcstats_words < 103 + c->g.n)
       return fail(BPDC_ERR_INVALID_ARG, "DC diagnostics buffer needs %d words", 103 + c->g.n);
   }
@@ -1323,7 +1323,8 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
       const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
       HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
                                  d_cut, d_iters, B, shot_offset, cp.tile.threads, cp.tile.grid, cp.tile.lds_bytes,
-                                 cp.tile.info_bytes, (unsigned long long*)d_ws, s));
+                                 cp.tile.info_bytes, (unsigned long long*)d_ws, s,
+                                 (unsigned long long*)p->dcstats));
       return BPDC_OK;
     }
     default:
@@ -1365,11 +1366,16 @@ bpdc_status bpdc_decode_multi(bpdc_plan p, const int32_t* d_code_of_shot, const 
   if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
     return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
-  if (p->dcstats) return fail(BPDC_ERR_UNSUPPORTED, "the multi-code launch keeps no DC diagnostics");
+  if (p->dcstats) {
+    int nmax = 0;
+    for (bpdc_code c : p->codes) nmax = std::max(nmax, c->g.n);
+    if (p->dcstats_words < 103 + nmax)
+      return fail(BPDC_ERR_INVALID_ARG, "DC diagnostics buffer needs %d words (largest code)", 103 + nmax);
+  }
   if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
     return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
   return multi_enqueue(p, d_code_of_shot, d_syn, d_syn_off, d_corr, d_corr_off, d_flags, d_iters, B, shot_offset,
-                       d_ws, (hipStream_t)stream);
+                       d_ws, (hipStream_t)stream, nullptr, (unsigned long long*)p->dcstats);
 }
 
 bpdc_status bpdc_graph_capture_multi(bpdc_plan p, const int32_t* d_code_of_shot, const uint64_t* d_syn,
@@ -1381,7 +1387,7 @@ bpdc_status bpdc_graph_capture_multi(bpdc_plan p, const int32_t* d_code_of_shot,
   if (!d_code_of_shot || !d_syn || !d_syn_off || !d_corr || !d_corr_off || !d_flags)
     return fail(BPDC_ERR_INVALID_ARG, "null pointer");
   if (!p->multi_ok) return fail(BPDC_ERR_UNSUPPORTED, "multi-code launch unavailable: %s", p->multi_why.c_str());
-  if (p->dcstats) return fail(BPDC_ERR_UNSUPPORTED, "the multi-code launch keeps no DC diagnostics");
+  if (p->dcstats) return fail(BPDC_ERR_UNSUPPORTED, "a captured graph keeps no DC diagnostics");
   if (!d_ws || ws_bytes < multi_ws_bytes(p, B))
     return fail(BPDC_ERR_WORKSPACE, "workspace of %zu bytes needed", multi_ws_bytes(p, B));
   hipStream_t s = (hipStream_t)stream;

@@ -85,16 +85,25 @@ def flat_fractions(spread_bins, eps_list):
     return {e: spread_bins[:int(round(100 * e))].sum() / tot for e in eps_list}
 
 
-@pytest.mark.parametrize("kernel", ["lane", "plain"])
-@pytest.mark.parametrize("name,p,shots,T", [("bb144", 0.05, 3000, (100, 100)), ("bb72", 0.06, 2000, (40, 40))])
+KERNELS = {"lane": "KERNEL_LANE", "plain": "KERNEL_PLAIN", "group": "KERNEL_GROUP"}
+
+
+def _code(name, p):
+    return synth.toric_code(3, p=p) if name == "toric3" else synth.bb_code(name, p=p)
+
+
+# toric L = 3 (9 checks): too small for the group kernel's in-LDS histogram, which then adds to the
+# device histogram row by row
+@pytest.mark.parametrize("kernel", ["lane", "plain", "group"])
+@pytest.mark.parametrize("name,p,shots,T", [("bb144", 0.05, 3000, (100, 100)), ("bb72", 0.06, 2000, (40, 40)),
+                                            ("toric3", 0.08, 3000, (18, 18))])
 def test_min_sum_dc_stats_vs_float32_oracle(P, kernel, name, p, shots, T):
     import torch
-    code = synth.bb_code(name, p=p)
+    code = _code(name, p)
     sh = synth.make_shots(code, shots, 7000 + shots)
     sp = P.PRIOR_POSTERIOR if code.second_pass == "posterior" else P.PRIOR_CHANNEL
     prm = P.Params(max_iter=T, alpha=0.625, second_pass_prior=sp, seed=31)
-    kid = P.KERNEL_LANE if kernel == "lane" else P.KERNEL_PLAIN
-    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=getattr(P, KERNELS[kernel]))
     st = _stats_buffer(code.n)
     plan.set_dc_stats(st)
     print(f"case {name} p={p} shots={shots} kernel={kernel}", flush=True)
@@ -122,15 +131,14 @@ def test_min_sum_dc_stats_vs_float32_oracle(P, kernel, name, p, shots, T):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("kernel", ["lane", "plain"])
+@pytest.mark.parametrize("kernel", ["lane", "plain", "group"])
 def test_product_sum_dc_stats_surface49(P, kernel):
     code = synth.rotated_surface_code(7, p=0.01)
     B = 20000
     sh = synth.make_shots(code, B, 7100)
     prm = P.Params(max_iter=(49, 49), alpha=1.0, second_pass_prior=P.PRIOR_POSTERIOR, seed=1,
                    rule=P.RULE_PRODUCT_SUM)
-    kid = P.KERNEL_LANE if kernel == "lane" else P.KERNEL_PLAIN
-    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=getattr(P, KERNELS[kernel]))
     st = _stats_buffer(code.n)
     plan.set_dc_stats(st)
     print(f"case surface7 product-sum kernel={kernel}", flush=True)
@@ -171,18 +179,62 @@ def test_product_sum_flatness_matches_table_4(P):
     assert abs(s[NSPREAD] / 1e6 - 0.11995211) < 2e-3
 
 
+def test_multi_code_dc_stats_sum_of_single_code_decodes(P):
+    """bpdc_decode_multi's diagnostics over a mixed batch (two HGP codes in LDS histograms, toric
+    L = 3 adding row by row) equal the sum of single-code group decodes of each code's shots
+    (lowest-index tie break: the picks do not depend on the shot's index)."""
+    import torch
+    codes = [synth.hgp_code(synth.random_regular_classical(nc, 4300 + j), name=f"hgp{j}", p=0.06,
+                            with_logicals=False) for j, nc in enumerate([16, 20])] + [synth.toric_code(3, p=0.08)]
+    prm = P.Params(max_iter=(30, 30), alpha=0.625, seed=4, tie_break=1)
+    pcodes = [P.Code.from_problem(c) for c in codes]
+    plan = P.Plan(pcodes, prm, kernel=P.KERNEL_GROUP)
+    cos_np, syn_np, per_code = synth.mixed_batch(codes, 300, 80, 8100)
+    nmax = max(c.n for c in codes)
+    st = _stats_buffer(nmax)
+    plan.set_dc_stats(st)
+    cos = torch.from_numpy(cos_np).cuda()
+    so, co, sw, nw = plan.multi_buffers(cos)
+    corr = torch.zeros(nw, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(len(cos_np), dtype=torch.uint8, device="cuda")
+    print("case multi-code dc stats", flush=True)
+    plan.decode_multi(cos, torch.from_numpy(syn_np).cuda(), so, corr, co, flags)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy()
+    want = np.zeros_like(got)
+    for i, c in enumerate(codes):
+        idx, sh = per_code[i]
+        single = P.Plan([pcodes[i]], prm, kernel=P.KERNEL_GROUP)
+        s1 = _stats_buffer(c.n)
+        single.set_dc_stats(s1)
+        gpu_decode(single, c, sh.syndromes, want_post=False)
+        s1 = s1.cpu().numpy()
+        want[:NSPREAD + 1] += s1[:NSPREAD + 1]
+        want[NSPREAD + 1:NSPREAD + 2 + c.n] += s1[NSPREAD + 1:]
+    assert want[NSPREAD] > 50, "case must exercise DC"
+    np.testing.assert_array_equal(got, want)
+
+
 def test_dc_stats_rejected_where_unsupported(P):
+    import torch
     code = synth.bb_code("bb144", p=0.05)
     prm = P.Params(max_iter=(20, 20), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=1)
     sh = synth.make_shots(code, 256, 7300)
     small = _stats_buffer(code.n)[:NSPREAD + 2]
-    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_LANE)
-    plan.set_dc_stats(small)
-    with pytest.raises(P.BpdcError):
+    for kid in (P.KERNEL_LANE, P.KERNEL_GROUP):
+        plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+        plan.set_dc_stats(small)
+        with pytest.raises(P.BpdcError):
+            gpu_decode(plan, code, sh.syndromes, want_post=False)
+        plan.set_dc_stats(None)
         gpu_decode(plan, code, sh.syndromes, want_post=False)
+    # a captured graph would keep the buffer: refused while one is set
     grp = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
     grp.set_dc_stats(_stats_buffer(code.n))
+    cos = torch.zeros(256, dtype=torch.int32, device="cuda")
+    so, co, sw, nw = grp.multi_buffers(cos)
+    syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
+    corr = torch.zeros(nw, dtype=torch.int64, device="cuda")
+    flags = torch.zeros(256, dtype=torch.uint8, device="cuda")
     with pytest.raises(P.BpdcError):
-        gpu_decode(grp, code, sh.syndromes, want_post=False)
-    grp.set_dc_stats(None)
-    gpu_decode(grp, code, sh.syndromes, want_post=False)
+        grp.capture_multi(cos, syn, so, corr, co, flags)
