@@ -678,7 +678,7 @@ def run_wms(args):
     prm = P.Params(max_iter=(25, 25), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, stop_on_converge=False,
                    seed=5)
     plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
-    f = P.weighted_bpdc(plan, ckpt_every=5)
+    f = P.weighted_bpdc(plan, ckpt_every=1)
     E, n = code.H.nnz, code.n
     rows = np.zeros((code.H.rows + code.O.shape[0], n), np.float32)
     for r in range(code.H.rows):
@@ -731,7 +731,7 @@ def run_wms(args):
         syn = torch.from_numpy(synth.pack_bits(sh.syndromes).view(np.int64)).cuda()
         fails = 0
         for lo in range(0, B, 250_000):
-            out = plan.wms_forward(wv.contiguous(), syn[lo:lo + 250_000], shot_offset=lo)
+            out = plan.wms_forward(wv.contiguous(), syn[lo:lo + 250_000], shot_offset=lo, ckpt_every=25)
             ehat = (out["post"][1] <= 0).cpu().numpy().astype(np.uint8)
             fl = out["flags"].cpu().numpy()
             fl_ = ((fl & 1) == 0) | synth.residual_is_logical(sh.errors[lo:lo + 250_000] ^ ehat, code.O)

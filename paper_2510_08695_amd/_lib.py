@@ -351,7 +351,7 @@ class Plan:
         _check(lib().bpdc_wms_ckpt_size(self.handle, code, B, ckpt_every, C.byref(n)))
         return n.value
 
-    def wms_forward(self, w, syn, code: int = 0, shot_offset: int = 0, ckpt_every: int = 5):
+    def wms_forward(self, w, syn, code: int = 0, shot_offset: int = 0, ckpt_every: int = 1):
         """Weighted forward: returns dict(post [2,B,n], cut [B,nw], flags [B], ckpt)."""
         import torch
         c = self.codes[code]
@@ -399,7 +399,7 @@ def eval_phi(x):
     return out
 
 
-def weighted_bpdc(plan: "Plan", code: int = 0, ckpt_every: int = 5):
+def weighted_bpdc(plan: "Plan", code: int = 0, ckpt_every: int = 1):
     """torch.autograd.Function over the weighted min-sum BP+DC decoder.
 
     Returns a callable f(w, syn) -> (post [2, B, n], cut, flags): w is the

@@ -376,8 +376,14 @@ __device__ __forceinline__ float sgn_of(float mag, u32 sign) {
   return mag == 0.0f ? 0.0f : (sign ? -1.0f : 1.0f);
 }
 
-template <int CDM, int RDM>
-__global__ void __launch_bounds__(512) k_wms_backward(WArgs a) {
+// At most 128 VGPRs: four waves per SIMD, as many as the per-wave LDS state
+// lets stay resident anyway.  SEG: checkpoints every K > 1 iterations (each
+// segment recomputed from its checkpoint); without, one checkpoint per
+// iteration, read back directly, the next one's loads issued before the
+// current iteration is reversed (codes of at most 128 checks: two rows per
+// lane in registers).
+template <int CDM, int RDM, bool SEG>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_wms_backward(WArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const WCode& C = a.C;
   const WTab tb = carve_tab(smem, C, false);
@@ -428,20 +434,53 @@ __global__ void __launch_bounds__(512) k_wms_backward(WArgs a) {
       float* gwp = gws + (size_t)pass * E;
       const float* gp = a.gpost + ((size_t)pass * a.B + b) * n;
       const float* gp2 = dc ? nullptr : a.gpost + ((size_t)a.B + b) * n;
+      const bool pf = !SEG && m <= 128;  // prefetched checkpoints
+      float p1[2] = {0.0f, 0.0f}, p2[2] = {0.0f, 0.0f};
+      u32 pb[2] = {0u, 0u};
+      auto ck_load = [&](int s) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int c = lane + 64 * r;
+          if (c < m) {
+            const size_t row = ck_index(a, pass, b, s) * (size_t)m + c;
+            p1[r] = a.ck_m1[row];
+            p2[r] = a.ck_m2[row];
+            pb[r] = a.ck_bits[row];
+          }
+        }
+      };
+      if (pf) ck_load(nck - 1);
       for (int s = nck - 1; s >= 0; --s) {
         const int t0 = s * K, len = min(T, t0 + K) - t0;
         // the checkpoint (state of iteration t0 + 1) and its r
-        for (int c = lane; c < m; c += 64) {
-          const size_t row = ck_index(a, pass, b, s) * (size_t)m + c;
-          CState st;
-          st.m1 = cm1[c] = a.ck_m1[row];
-          st.m2 = cm2[c] = a.ck_m2[row];
-          st.bits = cbits[c] = a.ck_bits[row];
-          const int e0 = tb.rp[c];
-          write_r<RDM>(msg, wp, e0, tb.rp[c + 1] - e0, st);
+        if (pf) {
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const int c = lane + 64 * r;
+            if (c < m) {
+              CState st;
+              st.m1 = cm1[c] = p1[r];
+              st.m2 = cm2[c] = p2[r];
+              st.bits = cbits[c] = pb[r];
+              const int e0 = tb.rp[c];
+              write_r<RDM>(msg, wp, e0, tb.rp[c + 1] - e0, st);
+            }
+          }
+          if (s > 0) ck_load(s - 1);
+        } else {
+          for (int c = lane; c < m; c += 64) {
+            const size_t row = ck_index(a, pass, b, s) * (size_t)m + c;
+            CState st;
+            st.m1 = cm1[c] = a.ck_m1[row];
+            st.m2 = cm2[c] = a.ck_m2[row];
+            st.bits = cbits[c] = a.ck_bits[row];
+            const int e0 = tb.rp[c];
+            write_r<RDM>(msg, wp, e0, tb.rp[c + 1] - e0, st);
+          }
         }
         wave_sync();
         // recompute the forward through the segment: states of iterations t0 + 2 .. t0 + len
+        if constexpr (SEG)
         for (int j = 1; j < len; ++j) {
           for (int v = lane; v < n; v += 64) {
             const int k0 = tb.cp[v], deg = tb.cp[v + 1] - k0;
@@ -509,28 +548,39 @@ __global__ void __launch_bounds__(512) k_wms_backward(WArgs a) {
           // second argmin of each row only); then the r of the previous iteration
           for (int c = lane; c < m; c += 64) {
             const CState sc = cs_at(j, c);
-            const int e0 = tb.rp[c], e1 = tb.rp[c + 1];
+            const int e0 = tb.rp[c], deg = tb.rp[c + 1] - e0;
             const u32 a1 = cs_a1(sc.bits), a2 = cs_a2(sc.bits);
+            // the row's gradients and scales loaded together (RDM bounds the degree)
+            float g[RDM], w[RDM];
+#pragma unroll
+            for (int k = 0; k < RDM; ++k)
+              if (k < deg) {
+                g[k] = grad[e0 + k];
+                w[k] = wp[e0 + k];
+              }
             float g1 = 0.0f, g2 = 0.0f;  // into the argmin's q, into the second argmin's q
-            for (int e = e0; e < e1; ++e) {
-              const int k = e - e0;
-              const float g = grad[e];
-              grad[e] = 0.0f;
-              if (g == 0.0f) continue;
-              const bool isa1 = (u32)k == a1;
-              const float mag = isa1 ? sc.m2 : sc.m1;
-              const float sg = (cs_neg(sc.bits) ^ cs_qsign(sc.bits, k)) ? -g : g;
-              atomicAdd(&gwp[e], sg * mag);
-              if (isa1) g2 += sg * wp[e];
-              else g1 += sg * wp[e];
-            }
+#pragma unroll
+            for (int k = 0; k < RDM; ++k)
+              if (k < deg) {
+                grad[e0 + k] = 0.0f;
+                const bool isa1 = (u32)k == a1;
+                const float mag = isa1 ? sc.m2 : sc.m1;
+                const float sg = (cs_neg(sc.bits) ^ cs_qsign(sc.bits, k)) ? -g[k] : g[k];
+                if (g[k] != 0.0f) atomicAdd(&gwp[e0 + k], sg * mag);
+                // a zero gradient adds +-0 (the sums start at +0: unchanged)
+                const float d = sg * w[k];
+                g2 = isa1 ? g2 + d : g2;
+                g1 = isa1 ? g1 : g1 + d;
+              }
             if (a1 != kNone) {
               grad[e0 + a1] = g1 * sgn_of(sc.m1, cs_qsign(sc.bits, a1));
               if (a2 != kNone) grad[e0 + a2] = g2 * sgn_of(sc.m2, cs_qsign(sc.bits, a2));
             }
-            if (j > 0) {
+            if (SEG && j > 0) {
               const CState sp = cs_at(j - 1, c);
-              for (int e = e0; e < e1; ++e) msg[e] = cs_r(sp, e - e0, wp[e]);
+#pragma unroll
+              for (int k = 0; k < RDM; ++k)
+                if (k < deg) msg[e0 + k] = cs_r(sp, k, w[k]);
             }
           }
           wave_sync();
@@ -664,17 +714,19 @@ hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, cons
   a.gw = gw;
   a.tab_bytes = bwd_tab_bytes(d);
   a.wave_bytes = bwd_wave_bytes(d, K);
-  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8;
-  const void* kern = small ? (const void*)k_wms_backward<4, 8> : (const void*)k_wms_backward<16, kWmsMaxRowDeg>;
+  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8, seg = K > 1;
+  const void* kern = small ? (seg ? (const void*)k_wms_backward<4, 8, true> : (const void*)k_wms_backward<4, 8, false>)
+                           : (seg ? (const void*)k_wms_backward<16, kWmsMaxRowDeg, true>
+                                  : (const void*)k_wms_backward<16, kWmsMaxRowDeg, false>);
   if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
   const int waves = wms_waves(a.tab_bytes, a.wave_bytes, max_lds);
   const size_t lds = a.tab_bytes + (size_t)waves * a.wave_bytes;
   (void)hipGetLastError();
   const int grid = wms_grid(kern, 64 * waves, lds, num_cu, B);
-  if (small) hipLaunchKernelGGL((k_wms_backward<4, 8>), dim3(grid), dim3(64 * waves), lds, stream, a);
-  else hipLaunchKernelGGL((k_wms_backward<16, kWmsMaxRowDeg>), dim3(grid), dim3(64 * waves), lds, stream, a);
-  return hipGetLastError();
+  void* args[] = {&a};
+  const hipError_t e = hipLaunchKernel(kern, dim3(grid), dim3(64 * waves), args, lds, stream);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace bpdc

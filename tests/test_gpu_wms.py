@@ -25,11 +25,11 @@ def setup():
     return P, code, prm, plan
 
 
-def _run_fwd(plan, code, syndromes, w):
+def _run_fwd(plan, code, syndromes, w, ckpt_every=5):
     import torch
     syn = torch.from_numpy(synth.pack_bits(syndromes).view(np.int64)).cuda()
     wt = torch.from_numpy(w.astype(np.float32)).cuda()
-    out = plan.wms_forward(wt, syn, ckpt_every=5)
+    out = plan.wms_forward(wt, syn, ckpt_every=ckpt_every)
     torch.cuda.synchronize()
     return syn, wt, out
 
@@ -85,7 +85,9 @@ def _loss_and_grad_post(post, errors, cut, flags):
     return loss, g
 
 
-def test_adjoint_matches_finite_differences_of_float64_oracle(setup):
+# checkpoints every iteration (the adjoint reads each back) and every 5 (segments recomputed)
+@pytest.mark.parametrize("ckpt_every", [1, 5])
+def test_adjoint_matches_finite_differences_of_float64_oracle(setup, ckpt_every):
     import torch
     P, code, prm, plan = setup
     B = 256
@@ -93,7 +95,7 @@ def test_adjoint_matches_finite_differences_of_float64_oracle(setup):
     E = code.H.nnz
     rng = np.random.default_rng(2)
     w = (0.625 + 0.05 * rng.standard_normal(2 * E)).astype(np.float32)
-    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w)
+    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w, ckpt_every)
     post = out["post"].cpu().numpy()
     flags = out["flags"].cpu().numpy()
     cut = synth.unpack_bits(out["cut"].cpu().numpy().view(np.uint64), code.n)
