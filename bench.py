@@ -770,7 +770,7 @@ def run_wms(args):
                      "iterations (parity loss)",
            "unit": "LER", "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "BB144 code capacity p=0.05, 2 x 432 edge scales from 0.625, batch 4096, "
-                                  "25+25 unrolled iterations, checkpoint every 5, Adam lr 1e-3; evaluation on "
+                                  "25+25 unrolled iterations, checkpoint every iteration, Adam lr 1e-3; evaluation on "
                                   "1e6 shots (seed 5999)", "train_steps": args.train_steps},
            "ler_untrained": ler_init, "ler_untrained_ci95": ci_init, "kernels": kern, "roofline": roof}
     for kind in ("parity", "bce"):

@@ -2,10 +2,12 @@
 // shot's whole state in LDS: any code size up to the LDS of one workgroup,
 // any mix of codes in one launch.
 //
-// A workgroup takes the next shot from a global counter (shots of a mixed
-// batch are first grouped by code, largest codes first, so that long shots
-// start early and consecutive shots of a workgroup share the code's index
-// arrays in cache).  Per iteration (flooding schedule, Sec. II.C) it runs
+// A workgroup takes the next shot from a global counter (a single-code
+// launch of a small code: the next few consecutive shots, whose outputs then
+// share cache lines written from one L2; shots of a mixed batch are first
+// grouped by code, largest codes first, so that long shots start early and
+// consecutive shots of a workgroup share the code's index arrays in cache).
+// Per iteration (flooding schedule, Sec. II.C) it runs
 //   variable phase: one thread per column: L_v = prior + sum r (ascending
 //                  check order), +inf on cut columns (Algorithm 2);
 //   check phase  : one thread per check: q = sat(L_v - r_old) for each edge,
@@ -18,6 +20,8 @@
 // of D and the second pass, then writes the packed correction.  The
 // arithmetic order is that of every other decoder of the library, so results
 // are bit-identical.
+#include <algorithm>
+
 #include "internal.h"
 // after the HIP runtime header: bpdc_device.h itself includes nothing
 #include "bpdc_device.h"
@@ -71,6 +75,7 @@ struct GArgs {
   unsigned long long* queue;
   const unsigned* n_bad;        // multi-code: shots with an out-of-range code index (kept out of `order`)
   unsigned long long* dcstats;  // DC diagnostics (spread bins, DC shots, cut sizes) or null
+  int claim;                    // consecutive shots per claim from the queue
   KParams p;
 };
 
@@ -289,14 +294,14 @@ __device__ __forceinline__ GCode uniform_code(const GCode* codes, int ci) {
 // chosen tie in ascending column order.
 __device__ __forceinline__ int dc_pick_row(const int32_t* dcol, int e0, int deg, const float* L, float lsat,
                                            float tie_eps, int tie_lowest, u64 seed, u64 shot, u64 row,
-                                           int* spread = nullptr) {
+                                           bool want_spread, int& spread) {
   float lmax = bpdc_dev::sat(L[gload(dcol, e0)], lsat), lmin = lmax;
   for (int k = 1; k < deg; ++k) {
     const float x = bpdc_dev::sat(L[gload(dcol, e0 + k)], lsat);
     lmax = fmaxf(lmax, x);
     lmin = fminf(lmin, x);
   }
-  if (spread) *spread = bpdc_dev::spread_bin_of(lmin, lmax);  // DC diagnostics (Appendix B)
+  if (want_spread) spread = bpdc_dev::spread_bin_of(lmin, lmax);  // DC diagnostics (Appendix B)
   const float scale = fmaxf(1.0f, fabsf(lmax));
   const float thr = lmax - tie_eps * scale;
   int nt = 0;
@@ -344,291 +349,300 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
   // ordering kernels and left out of `order`, which lists the others first
   const long long nshots = a.n_bad ? a.B - (long long)*a.n_bad : a.B;
   for (;;) {
-    if (tid == 0) sIdx = (long long)atomicAdd(a.queue, 1ull);
+    // claims of a.claim consecutive shots: the outputs of neighbouring shots
+    // (small codes: a few words each) are then written from one L2
+    if (tid == 0) sIdx = (long long)atomicAdd(a.queue, (unsigned long long)a.claim);
     __syncthreads();
-    const long long idx = uniform(sIdx);
+    const long long first = uniform(sIdx);
     __syncthreads();
-    if (idx >= nshots) break;
-    const long long b = a.order ? (long long)uniform(a.order[idx]) : idx;
-    const int ci = a.code_of_shot ? uniform(a.code_of_shot[b]) : 0;
-    const GCode C = uniform_code(a.codes, ci);
-    const int n = C.n, m = C.m;
-    const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
-    // LDS carve for this code; check m and column n are the dummies the
-    // padding entries of the adjacency tables point at.  Product-sum keeps
-    // the r of every edge (CSR order) where min-sum keeps check records.
-    const int E = PS ? C.h_row_ptr[m] : 0;
-    unsigned char* state = smem + kLdsHead;
-    const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell),
-                                 lt = table_rsrc((const int32_t*)C.lam);
-    const u32 n4 = (u32)n * 4u, m4 = (u32)m * 4u;
-    Rec* S = (Rec*)state;                          // [m + 1] check states (min-sum)
-    float* R = (float*)state;                      // [E] per-edge r (product-sum)
-    float* L = PS ? (float*)(state + (((size_t)E * 4 + 15) & ~(size_t)15)) : (float*)(S + m + 1);  // [n + 1]
-    u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
-    u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
-    // [n] per-shot prior: the first pass's under soft DC, the second pass's
-    // with the posterior prior
-    float* lam2 = (float*)(synw + ((m + 31) >> 5));
-    const bool soft = P.soft_period > 0;
-    // the 64-bit-record variant (rows above 32 edges: circuit-level DEMs, whose
-    // column degrees differ from block to block) bounds each wave's column
-    // chunks by its block's largest degree; the 32-bit variant keeps the
-    // code's (fewer registers live)
-    const bool blk_deg = Wide && (nt & 63) == 0;
-    // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
-    // padded row entry reads L = +inf, so q saturates at lsat: it is never a
-    // new minimum, leaves the second minimum (a median with lsat) and the
-    // sign parity unchanged
-    if (tid == 0) {
-      if (!PS) S[m].set(-0.0f, -0.0f, 0, 0, m + kRec0);
-      L[n] = INF;
-    }
+    if (first >= nshots) break;
+    const long long last = first + a.claim < nshots ? first + a.claim : nshots;
+    for (long long idx = first; idx < last; ++idx) {
+      const long long b = a.order ? (long long)uniform(a.order[idx]) : idx;
+      const int ci = a.code_of_shot ? uniform(a.code_of_shot[b]) : 0;
+      const GCode C = uniform_code(a.codes, ci);
+      const int n = C.n, m = C.m;
+      const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
+      // LDS carve for this code; check m and column n are the dummies the
+      // padding entries of the adjacency tables point at.  Product-sum keeps
+      // the r of every edge (CSR order) where min-sum keeps check records.
+      const int E = PS ? C.h_row_ptr[m] : 0;
+      unsigned char* state = smem + kLdsHead;
+      const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell),
+                                   lt = table_rsrc((const int32_t*)C.lam);
+      const u32 n4 = (u32)n * 4u, m4 = (u32)m * 4u;
+      Rec* S = (Rec*)state;                          // [m + 1] check states (min-sum)
+      float* R = (float*)state;                      // [E] per-edge r (product-sum)
+      float* L = PS ? (float*)(state + (((size_t)E * 4 + 15) & ~(size_t)15)) : (float*)(S + m + 1);  // [n + 1]
+      u32* cutw = (u32*)(L + n + 1);                 // [ceil(n/32)]
+      u32* synw = cutw + ((n + 31) >> 5);            // [ceil(m/32)]
+      // [n] per-shot prior: the first pass's under soft DC, the second pass's
+      // with the posterior prior
+      float* lam2 = (float*)(synw + ((m + 31) >> 5));
+      const bool soft = P.soft_period > 0;
+      // the 64-bit-record variant (rows above 32 edges: circuit-level DEMs, whose
+      // column degrees differ from block to block) bounds each wave's column
+      // chunks by its block's largest degree; the 32-bit variant keeps the
+      // code's (fewer registers live)
+      const bool blk_deg = Wide && (nt & 63) == 0;
+      // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
+      // padded row entry reads L = +inf, so q saturates at lsat: it is never a
+      // new minimum, leaves the second minimum (a median with lsat) and the
+      // sign parity unchanged
+      if (tid == 0) {
+        if (!PS) S[m].set(-0.0f, -0.0f, 0, 0, m + kRec0);
+        L[n] = INF;
+      }
 
-    const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
-    for (int w = tid; w < ((m + 31) >> 5); w += nt) {
-      const uint64_t x = sp[w >> 1];
-      synw[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
-    }
-    for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
+      const uint64_t* sp = a.syn + (a.syn_off ? a.syn_off[b] : b * sw64);
+      for (int w = tid; w < ((m + 31) >> 5); w += nt) {
+        const uint64_t x = sp[w >> 1];
+        synw[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
+      }
+      for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
 
-    int it[2] = {0, 0};
-    bool conv = false;
-    for (int pass = 0; pass < 2; ++pass) {
-      const int T = pass ? P.T2 : P.T1;
-      const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
-      if (PS)
-        for (int e = tid; e < E; e += nt) R[e] = 0.0f;
-      else
-        for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + kRec0);
-      if (pass == 0 && soft)
-        for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
-      __syncthreads();
-      int t = 0;
-      for (;;) {
-        // ---- variable phase: L = prior + sum of r (all zero at t = 0) ----
-        // Only the second pass has cut columns (+inf: with the posterior prior
-        // lam2 holds them); the first pass's priors are finite.
-        const bool cuts = pass == 1;
-        if (!PS && !use_lam2 && !cuts && !blk_deg && C.max_col_deg <= 4) {
-          // first pass (no cut columns, the channel prior), columns of at most
-          // 4 entries: software-pipelined, the next column's table entries and
-          // prior are in flight while this column's check records are read
-          // and summed (the same sums in the same order)
-          const int K = C.max_col_deg;
-          u32 e[4] = {0u, 0u, 0u, 0u};
-          float lam = 0.0f;
-          if (tid < n) col_fetch(e, lam, K, vt, lt, n4, (u32)tid << 2);
+      // iterations of each pass (scalars, not an array indexed by the pass: that
+      // would live in per-thread scratch memory)
+      int it0 = 0, it1 = 0;
+      bool conv = false;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int T = pass ? P.T2 : P.T1;
+        const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
+        if (PS)
+          for (int e = tid; e < E; e += nt) R[e] = 0.0f;
+        else
+          for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + kRec0);
+        if (pass == 0 && soft)
+          for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
+        __syncthreads();
+        int t = 0;
+        for (;;) {
+          // ---- variable phase: L = prior + sum of r (all zero at t = 0) ----
+          // Only the second pass has cut columns (+inf: with the posterior prior
+          // lam2 holds them); the first pass's priors are finite.
+          const bool cuts = pass == 1;
+          if (!PS && !use_lam2 && !cuts && !blk_deg && C.max_col_deg <= 4) {
+            // first pass (no cut columns, the channel prior), columns of at most
+            // 4 entries: software-pipelined, the next column's table entries and
+            // prior are in flight while this column's check records are read
+            // and summed (the same sums in the same order)
+            const int K = C.max_col_deg;
+            u32 e[4] = {0u, 0u, 0u, 0u};
+            float lam = 0.0f;
+            if (tid < n) col_fetch(e, lam, K, vt, lt, n4, (u32)tid << 2);
+            for (int v = tid; v < n; v += nt) {
+              const u32 ce[4] = {e[0], e[1], e[2], e[3]};
+              float Lv = lam;
+              if (v + nt < n) col_fetch(e, lam, K, vt, lt, n4, (u32)(v + nt) << 2);
+              switch (K) {  // uniform
+                case 4: Lv = col_add<4, Rec>(Lv, ce); break;
+                case 3: Lv = col_add<3, Rec>(Lv, ce); break;
+                case 2: Lv = col_add<2, Rec>(Lv, ce); break;
+                case 1: Lv = col_add<1, Rec>(Lv, ce); break;
+                default: break;
+              }
+              L[v] = Lv;
+            }
+          } else
           for (int v = tid; v < n; v += nt) {
-            const u32 ce[4] = {e[0], e[1], e[2], e[3]};
-            float Lv = lam;
-            if (v + nt < n) col_fetch(e, lam, K, vt, lt, n4, (u32)(v + nt) << 2);
-            switch (K) {  // uniform
-              case 4: Lv = col_add<4, Rec>(Lv, ce); break;
-              case 3: Lv = col_add<3, Rec>(Lv, ce); break;
-              case 2: Lv = col_add<2, Rec>(Lv, ce); break;
-              case 1: Lv = col_add<1, Rec>(Lv, ce); break;
-              default: break;
+            const u32 vo = (u32)v << 2;
+            float Lv;
+            if (use_lam2) Lv = lam2[v];
+            else if (cuts && ((cutw[v >> 5] >> (v & 31)) & 1u)) Lv = INF;
+            else Lv = __uint_as_float(vtab_at(lt, 0u, vo));
+            if (PS && (!cuts || Lv != INF)) {
+              for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
+            } else if (!PS && (!cuts || Lv != INF)) {
+              // entries in chunks of 4 and a last chunk of kend mod 4; padding
+              // entries of columns shorter than kend read the dummy check and add
+              // -0 (x + -0 = x).  A wave holds 64 consecutive columns (v = tid +
+              // k nt with nt a multiple of 64), so it can stop at the largest
+              // degree of its block (a wave-uniform bound) instead of the code's
+              const int kend = blk_deg ? __builtin_amdgcn_readfirstlane(gload(C.v_blk_deg, v >> 6)) : C.max_col_deg;
+              int k0 = 0;
+              for (; k0 + 4 <= kend; k0 += 4) Lv = col_sum<4, Rec>(Lv, vt, n4, vo, k0);
+              switch (kend - k0) {  // uniform
+                case 1: Lv = col_sum<1, Rec>(Lv, vt, n4, vo, k0); break;
+                case 2: Lv = col_sum<2, Rec>(Lv, vt, n4, vo, k0); break;
+                case 3: Lv = col_sum<3, Rec>(Lv, vt, n4, vo, k0); break;
+                default: break;
+              }
             }
             L[v] = Lv;
           }
-        } else
-        for (int v = tid; v < n; v += nt) {
-          const u32 vo = (u32)v << 2;
-          float Lv;
-          if (use_lam2) Lv = lam2[v];
-          else if (cuts && ((cutw[v >> 5] >> (v & 31)) & 1u)) Lv = INF;
-          else Lv = __uint_as_float(vtab_at(lt, 0u, vo));
-          if (PS && (!cuts || Lv != INF)) {
-            for (int k = C.h_col_ptr[v]; k < C.h_col_ptr[v + 1]; ++k) Lv = Lv + R[gload(C.h_col_edge, k)];
-          } else if (!PS && (!cuts || Lv != INF)) {
-            // entries in chunks of 4 and a last chunk of kend mod 4; padding
-            // entries of columns shorter than kend read the dummy check and add
-            // -0 (x + -0 = x).  A wave holds 64 consecutive columns (v = tid +
-            // k nt with nt a multiple of 64), so it can stop at the largest
-            // degree of its block (a wave-uniform bound) instead of the code's
-            const int kend = blk_deg ? __builtin_amdgcn_readfirstlane(gload(C.v_blk_deg, v >> 6)) : C.max_col_deg;
-            int k0 = 0;
-            for (; k0 + 4 <= kend; k0 += 4) Lv = col_sum<4, Rec>(Lv, vt, n4, vo, k0);
-            switch (kend - k0) {  // uniform
-              case 1: Lv = col_sum<1, Rec>(Lv, vt, n4, vo, k0); break;
-              case 2: Lv = col_sum<2, Rec>(Lv, vt, n4, vo, k0); break;
-              case 3: Lv = col_sum<3, Rec>(Lv, vt, n4, vo, k0); break;
-              default: break;
+          if (tid == 0) sUnsat[t & 1] = 0;
+          __syncthreads();
+          // ---- check phase: next check state from q = sat(L - r_old), with the stop
+          // test H e = s (e = [L <= 0]) on the way; the new state is not used
+          // when the pass ends here ----
+          int bad = 0;
+          if constexpr (PS) {
+            for (int c = tid; c < m; c += nt) {
+              const int e0 = gload(C.h_row_ptr, c), deg = gload(C.h_row_ptr, c + 1) - e0;
+              const u32 sbit = (synw[c >> 5] >> (c & 31)) & 1u;
+              u32 par = sbit, neg = sbit, qn = 0u;
+              float ph[8];
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                ph[j] = 0.0f;
+                if (j < deg) {
+                  const float Lv = L[gload(C.h_col, e0 + j)];
+                  par ^= (Lv <= 0.0f) ? 1u : 0u;
+                  const float q = bpdc_dev::ps_q(Lv, R[e0 + j], LS);  // +inf from a cut column
+                  const u32 qneg = (q < 0.0f) ? 1u : 0u;
+                  neg ^= qneg;
+                  qn |= qneg << j;
+                  ph[j] = bpdc_dev::phi(fabsf(q));
+                }
+              }
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                if (j < deg) {
+                  // phi of the sum of the other edges' phi, left to right in row order
+                  float sum = 0.0f;
+  #pragma unroll
+                  for (int o = 0; o < 8; ++o)
+                    if (o != j && o < deg) sum = sum + ph[o];
+                  float mag = bpdc_dev::phi(sum);
+                  if (!(mag < LS)) mag = LS;
+                  const float val = P.alpha * mag;
+                  R[e0 + j] = (neg ^ ((qn >> j) & 1u)) ? -val : val;
+                }
+              }
+              bad |= (int)par;
             }
-          }
-          L[v] = Lv;
-        }
-        if (tid == 0) sUnsat[t & 1] = 0;
-        __syncthreads();
-        // ---- check phase: next check state from q = sat(L - r_old), with the stop
-        // test H e = s (e = [L <= 0]) on the way; the new state is not used
-        // when the pass ends here ----
-        int bad = 0;
-        if constexpr (PS) {
+          } else
           for (int c = tid; c < m; c += nt) {
-            const int e0 = gload(C.h_row_ptr, c), deg = gload(C.h_row_ptr, c + 1) - e0;
-            const u32 sbit = (synw[c >> 5] >> (c & 31)) & 1u;
-            u32 par = sbit, neg = sbit, qn = 0u;
-            float ph[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              ph[j] = 0.0f;
-              if (j < deg) {
-                const float Lv = L[gload(C.h_col, e0 + j)];
-                par ^= (Lv <= 0.0f) ? 1u : 0u;
-                const float q = bpdc_dev::ps_q(Lv, R[e0 + j], LS);  // +inf from a cut column
-                const u32 qneg = (q < 0.0f) ? 1u : 0u;
-                neg ^= qneg;
-                qn |= qneg << j;
-                ph[j] = bpdc_dev::phi(fabsf(q));
-              }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              if (j < deg) {
-                // phi of the sum of the other edges' phi, left to right in row order
-                float sum = 0.0f;
-#pragma unroll
-                for (int o = 0; o < 8; ++o)
-                  if (o != j && o < deg) sum = sum + ph[o];
-                float mag = bpdc_dev::phi(sum);
-                if (!(mag < LS)) mag = LS;
-                const float val = P.alpha * mag;
-                R[e0 + j] = (neg ^ ((qn >> j) & 1u)) ? -val : val;
-              }
-            }
+            const Rec so = S[c];
+            RowAcc<Rec> acc{LS, LS, 0, 0, 0u};
+            // the check table holds the LDS address of each entry's L; the
+            // code's largest row degree in chunks of 8, then 4, 2, 1 (uniform
+            // branches; padding entries of shorter rows read the dummy column,
+            // L = +inf, whose q saturates and changes nothing)
+            const u32 co = (u32)c << 2;
+            const W io = so.signs();
+            const int am_old = so.argmin(), K = C.max_row_deg;
+            int k0 = 0;
+            for (; k0 + 8 <= K; k0 += 8) row_chunk<8, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
+            if ((K - k0) & 4) { row_chunk<4, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 4; }
+            if ((K - k0) & 2) { row_chunk<2, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 2; }
+            if ((K - k0) & 1) row_chunk<1, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
+            const W sb = Rec::finish_signs(acc.sb, K);
+            const float m1 = acc.m1, m2 = acc.m2;
+            const int amin = acc.amin;
+            const u32 par = ((u32)(acc.pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
             bad |= (int)par;
+            const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
+            // flip every sign bit on an odd parity: the bits past the row's
+            // degree are read only by padding entries, whose q saturates anyway
+            const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
+            S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + kRec0);
           }
-        } else
-        for (int c = tid; c < m; c += nt) {
-          const Rec so = S[c];
-          RowAcc<Rec> acc{LS, LS, 0, 0, 0u};
-          // the check table holds the LDS address of each entry's L; the
-          // code's largest row degree in chunks of 8, then 4, 2, 1 (uniform
-          // branches; padding entries of shorter rows read the dummy column,
-          // L = +inf, whose q saturates and changes nothing)
-          const u32 co = (u32)c << 2;
-          const W io = so.signs();
-          const int am_old = so.argmin(), K = C.max_row_deg;
-          int k0 = 0;
-          for (; k0 + 8 <= K; k0 += 8) row_chunk<8, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
-          if ((K - k0) & 4) { row_chunk<4, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 4; }
-          if ((K - k0) & 2) { row_chunk<2, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 2; }
-          if ((K - k0) & 1) row_chunk<1, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
-          const W sb = Rec::finish_signs(acc.sb, K);
-          const float m1 = acc.m1, m2 = acc.m2;
-          const int amin = acc.amin;
-          const u32 par = ((u32)(acc.pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
-          bad |= (int)par;
-          const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
-          // flip every sign bit on an odd parity: the bits past the row's
-          // degree are read only by padding entries, whose q saturates anyway
-          const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
-          S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + kRec0);
-        }
-        if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
-        __syncthreads();
-        if (t >= 1) {
-          const bool ok = sUnsat[t & 1] == 0;
-          if ((P.stop && ok) || t >= T) {
-            conv = ok;
-            it[pass] = t;
-            break;
-          }
-          // intermittent soft DC (application j = t / soft_period of the first
-          // pass): the rows of D nominate on this iteration's posteriors (row h
-          // hashed as j * rows(D) + h), the nominees' priors rise by soft_shift;
-          // cutw (empty during the first pass) collects the nominees
-          if (pass == 0 && soft && !ok && t % P.soft_period == 0) {
-            const u64 rbase = (u64)(t / P.soft_period) * (u64)C.md;
-            for (int h = tid; h < C.md; h += nt) {
-              const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
-              if (deg == 0) continue;
-              const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
-                                           (u64)(a.shot_offset + b), rbase + (u64)h);
-              atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+          if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
+          __syncthreads();
+          if (t >= 1) {
+            const bool ok = sUnsat[t & 1] == 0;
+            if ((P.stop && ok) || t >= T) {
+              conv = ok;
+              if (pass) it1 = t;
+              else it0 = t;
+              break;
             }
-            __syncthreads();
-            for (int v = tid; v < n; v += nt)
-              if ((cutw[v >> 5] >> (v & 31)) & 1u) lam2[v] = lam2[v] + P.soft_shift;
-            __syncthreads();
-            for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
-            __syncthreads();
+            // intermittent soft DC (application j = t / soft_period of the first
+            // pass): the rows of D nominate on this iteration's posteriors (row h
+            // hashed as j * rows(D) + h), the nominees' priors rise by soft_shift;
+            // cutw (empty during the first pass) collects the nominees
+            if (pass == 0 && soft && !ok && t % P.soft_period == 0) {
+              const u64 rbase = (u64)(t / P.soft_period) * (u64)C.md;
+              for (int h = tid; h < C.md; h += nt) {
+                const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
+                if (deg == 0) continue;
+                int unused_bin = 0;
+                const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+                                             (u64)(a.shot_offset + b), rbase + (u64)h, false, unused_bin);
+                atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+              }
+              __syncthreads();
+              for (int v = tid; v < n; v += nt)
+                if ((cutw[v >> 5] >> (v & 31)) & 1u) lam2[v] = lam2[v] + P.soft_shift;
+              __syncthreads();
+              for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
+              __syncthreads();
+            }
           }
+          ++t;
         }
-        ++t;
-      }
-      if (pass == 1 || conv) break;
-      // ---- degeneracy cutting (first pass failed) ----
-      // With diagnostics on, each row's spread bin goes to a histogram of the
-      // shot in LDS over the check-state region (free between the passes),
-      // flushed once per shot; a code whose region holds fewer than 101 bins
-      // adds to the device histogram directly.
-      const bool dcs = a.dcstats != nullptr;
-      u32* hist = (u32*)state;
-      const bool lds_hist = dcs && (PS ? (size_t)E * 4 : (size_t)(m + 1) * 16) >= 101 * sizeof(u32);
-      if (lds_hist) {
-        for (int i = tid; i < 101; i += nt) hist[i] = 0u;
-        if (tid == 0) sCount = 0u;
+        if (pass == 1 || conv) break;
+        // ---- degeneracy cutting (first pass failed) ----
+        // With diagnostics on, each row's spread bin goes to a histogram of the
+        // shot in LDS over the check-state region (free between the passes),
+        // flushed once per shot; a code whose region holds fewer than 101 bins
+        // adds to the device histogram directly.
+        const bool dcs = a.dcstats != nullptr;
+        u32* hist = (u32*)state;
+        const bool lds_hist = dcs && (PS ? (size_t)E * 4 : (size_t)(m + 1) * 16) >= 101 * sizeof(u32);
+        if (lds_hist) {
+          for (int i = tid; i < 101; i += nt) hist[i] = 0u;
+          if (tid == 0) sCount = 0u;
+          __syncthreads();
+        } else if (dcs && tid == 0) {
+          sCount = 0u;  // ordered before its use by the barrier after the rows
+        }
+        for (int h = tid; h < C.md; h += nt) {
+          const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
+          if (deg == 0) continue;
+          int bin = 0;
+          const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+                                       (u64)(a.shot_offset + b), (u64)h, dcs, bin);
+          atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
+          if (lds_hist) atomicAdd(&hist[bin], 1u);
+          else if (dcs) atomicAdd(&a.dcstats[bin], 1ull);
+        }
         __syncthreads();
-      } else if (dcs && tid == 0) {
-        sCount = 0u;  // ordered before its use by the barrier after the rows
+        if (dcs) {
+          if (lds_hist)
+            for (int i = tid; i < 101; i += nt)
+              if (hist[i]) atomicAdd(&a.dcstats[i], (unsigned long long)hist[i]);
+          unsigned nc = 0;
+          for (int w = tid; w < ((n + 31) >> 5); w += nt) nc += (unsigned)__builtin_popcount(cutw[w]);
+          if (nc) atomicAdd(&sCount, nc);
+        }
+        if (P.second_pass_posterior)
+          for (int v = tid; v < n; v += nt)
+            lam2[v] = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : bpdc_dev::sat(L[v], LS);
+        __syncthreads();
+        if (dcs && tid == 0) {  // the shot ran DC; its cut size
+          atomicAdd(&a.dcstats[101], 1ull);
+          atomicAdd(&a.dcstats[102 + sCount], 1ull);
+        }
       }
-      for (int h = tid; h < C.md; h += nt) {
-        const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
-        if (deg == 0) continue;
-        int bin = 0;
-        const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
-                                     (u64)(a.shot_offset + b), (u64)h, dcs ? &bin : nullptr);
-        atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
-        if (lds_hist) atomicAdd(&hist[bin], 1u);
-        else if (dcs) atomicAdd(&a.dcstats[bin], 1ull);
+      // ---- outputs ----
+      const bool dc = it1 > 0;
+      uint64_t* cp = a.corr + (a.corr_off ? a.corr_off[b] : b * nw64);
+      for (int w = wave; w < nw64; w += nwaves) {
+        const int v = w * 64 + lane;
+        const u64 word = __ballot(v < n && L[v] <= 0.0f);
+        if (lane == 0) cp[w] = word;
+        if (a.cut) {
+          const u32 lo = cutw[2 * w];
+          const u32 hi = (2 * w + 1 < ((n + 31) >> 5)) ? cutw[2 * w + 1] : 0u;
+          if (lane == 0) a.cut[b * nw64 + w] = dc ? (((u64)hi << 32) | lo) : 0ull;
+        }
+      }
+      if (a.post)
+        for (int v = tid; v < n; v += nt) {
+          const float x = L[v];
+          a.post[b * n + v] = (x == INF) ? x : bpdc_dev::sat(x, LS);
+        }
+      if (tid == 0) {
+        a.flags[b] = (uint8_t)((conv ? 1 : 0) | (dc ? 2 : 0));
+        if (a.iters) {
+          a.iters[2 * b] = (int16_t)it0;
+          a.iters[2 * b + 1] = (int16_t)it1;
+        }
       }
       __syncthreads();
-      if (dcs) {
-        if (lds_hist)
-          for (int i = tid; i < 101; i += nt)
-            if (hist[i]) atomicAdd(&a.dcstats[i], (unsigned long long)hist[i]);
-        unsigned nc = 0;
-        for (int w = tid; w < ((n + 31) >> 5); w += nt) nc += (unsigned)__builtin_popcount(cutw[w]);
-        if (nc) atomicAdd(&sCount, nc);
-      }
-      if (P.second_pass_posterior)
-        for (int v = tid; v < n; v += nt)
-          lam2[v] = ((cutw[v >> 5] >> (v & 31)) & 1u) ? INF : bpdc_dev::sat(L[v], LS);
-      __syncthreads();
-      if (dcs && tid == 0) {  // the shot ran DC; its cut size
-        atomicAdd(&a.dcstats[101], 1ull);
-        atomicAdd(&a.dcstats[102 + sCount], 1ull);
-      }
     }
-    // ---- outputs ----
-    const bool dc = it[1] > 0;
-    uint64_t* cp = a.corr + (a.corr_off ? a.corr_off[b] : b * nw64);
-    for (int w = wave; w < nw64; w += nwaves) {
-      const int v = w * 64 + lane;
-      const u64 word = __ballot(v < n && L[v] <= 0.0f);
-      if (lane == 0) cp[w] = word;
-      if (a.cut) {
-        const u32 lo = cutw[2 * w];
-        const u32 hi = (2 * w + 1 < ((n + 31) >> 5)) ? cutw[2 * w + 1] : 0u;
-        if (lane == 0) a.cut[b * nw64 + w] = dc ? (((u64)hi << 32) | lo) : 0ull;
-      }
-    }
-    if (a.post)
-      for (int v = tid; v < n; v += nt) {
-        const float x = L[v];
-        a.post[b * n + v] = (x == INF) ? x : bpdc_dev::sat(x, LS);
-      }
-    if (tid == 0) {
-      a.flags[b] = (uint8_t)((conv ? 1 : 0) | (dc ? 2 : 0));
-      if (a.iters) {
-        a.iters[2 * b] = (int16_t)it[0];
-        a.iters[2 * b + 1] = (int16_t)it[1];
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -685,9 +699,16 @@ hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
                         size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream,
-                        unsigned long long* dcstats) {
+                        unsigned long long* dcstats, int claim_n) {
   GArgs a;
   a.dcstats = dcstats;
+  // single-code launches of small codes: up to 8 consecutive shots per claim,
+  // about one 128-byte line of corrections (n is the code's column count)
+  a.claim = 1;
+  if (!code_of_shot && claim_n > 0) {
+    const int nw = (claim_n + 63) / 64;
+    a.claim = std::max(1, std::min(8, 16 / nw));
+  }
   a.codes = (const GCode*)d_codes;
   a.code_of_shot = code_of_shot;
   a.n_bad = n_bad;

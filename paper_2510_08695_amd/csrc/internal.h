@@ -96,7 +96,9 @@ hipError_t group_launch(const void* d_codes, const unsigned* n_bad, const int32_
                         const int64_t* corr_off, uint8_t* flags, float* post, uint64_t* cut,
                         int16_t* iters, int64_t B, int64_t shot_offset, int threads, int grid,
                         size_t lds, int info_bytes, unsigned long long* queue, hipStream_t stream,
-                        unsigned long long* dcstats = nullptr);
+                        unsigned long long* dcstats = nullptr, int claim_n = 0);
+// (claim_n: a single-code launch's column count, which sets how many
+// consecutive shots a workgroup claims at once; 0 or a multi-code launch: one)
 // hist and base hold ncodes + 1 entries each; hist[ncodes] counts the shots with an
 // out-of-range code index, which get flags kFlagBadCode and no place in `order`.
 hipError_t group_order(const int32_t* code_of_shot, int64_t B, const int32_t* code_by_rank, int ncodes,

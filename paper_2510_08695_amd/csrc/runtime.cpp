@@ -490,7 +490,7 @@ float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, Tu
     (void)hipEventRecord(e0, 0);
     hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
                                       nullptr, nullptr, nullptr, S, 0, tile.threads, tile.grid, tile.lds_bytes,
-                                      tile.info_bytes, tb.queue, 0);
+                                      tile.info_bytes, tb.queue, 0, nullptr, p->codes[code]->g.n);
     (void)hipEventRecord(e1, 0);
     if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       best = -1.0f;
@@ -1324,7 +1324,7 @@ bpdc_status bpdc_decode(bpdc_plan p, int32_t code, const uint64_t* d_syn, int64_
       HIP_TRY(bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, d_syn, nullptr, d_corr, nullptr, d_flags, d_post,
                                  d_cut, d_iters, B, shot_offset, cp.tile.threads, cp.tile.grid, cp.tile.lds_bytes,
                                  cp.tile.info_bytes, (unsigned long long*)d_ws, s,
-                                 (unsigned long long*)p->dcstats));
+                                 (unsigned long long*)p->dcstats, c->g.n));
       return BPDC_OK;
     }
     default:
