@@ -360,7 +360,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     for (long long idx = first; idx < last; ++idx) {
       const long long b = a.order ? (long long)uniform(a.order[idx]) : idx;
       const int ci = a.code_of_shot ? uniform(a.code_of_shot[b]) : 0;
-      const GCode C = uniform_code(a.codes, ci);
+      // min-sum reads its tables as buffer resources built from a scalar code
+      // description; product-sum reads them with plain loads, and the scalar
+      // copy would only add scalar-register spills there
+      const GCode C = PS ? a.codes[ci] : uniform_code(a.codes, ci);
       const int n = C.n, m = C.m;
       const int sw64 = (m + 63) >> 6, nw64 = (n + 63) >> 6;
       // LDS carve for this code; check m and column n are the dummies the

@@ -512,21 +512,16 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   bpdc::GroupTile base;
   base.info_bytes = group_variant(p, d);
   base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes, d.E);
-  // powers of two, and the multiples of 64 that split the columns or the
-  // checks into whole rounds of one item per thread (the last round of each
-  // phase is otherwise partly idle at the phase's barrier)
+  // powers of two (thread counts that split a phase into whole rounds, such
+  // as 896 for 2592 checks, measured slower than 1024 on every code tried:
+  // fewer waves hide less latency; and their timings on a short synthetic
+  // batch, whose few long DC shots dominate it, are too close to rank)
   std::vector<int> cands;
   const int work = std::max(d.n, d.m);
-  auto add = [&](int t) {
-    if (t < 64 || t > 1024 || (t > 64 && t / 2 >= work)) return;  // more threads than items
-    if (std::find(cands.begin(), cands.end(), t) == cands.end()) cands.push_back(t);
-  };
-  for (int t : {64, 128, 256, 512, 1024}) add(t);
-  for (int w : {d.n, d.m})
-    for (int r = 1; r <= 12; ++r) {
-      const int t = 64 * ((w + 64 * r - 1) / (64 * r));
-      if (t >= 256) add(t);
-    }
+  for (int t : {64, 128, 256, 512, 1024}) {
+    if (t > 64 && t / 2 >= work) continue;  // more threads than items
+    cands.push_back(t);
+  }
   if (const char* e = getenv("BPDC_GROUP_THREADS"))  // pins the threads per workgroup
     cands = {std::min(1024, std::max(64, atoi(e) / 64 * 64))};
   auto make = [&](int threads) {
