@@ -253,7 +253,10 @@ bpdc_status bpdc_graph_launch(bpdc_plan plan, void* stream);
  * with no early stop, and stores check-state checkpoints every `ckpt_every`
  * iterations for the backward (12 bytes per check: both minima of |q| over
  * the row, their positions, the q signs and their parity with the syndrome
- * bit).  Rows of H of at most 21 edges, channel second-pass prior, min-sum,
+ * bit).  ckpt_every = 1 (a checkpoint per iteration: 12 m (T1 + T2) bytes per
+ * shot at most) lets the backward read every state back instead of
+ * recomputing segments, and is its fastest setting; larger values trade
+ * backward time for checkpoint memory.  Rows of H of at most 21 edges, channel second-pass prior, min-sum,
  * no soft DC (BPDC_ERR_UNSUPPORTED otherwise).
  *   d_w      [2][E] float scales in CSR edge order of H (pass 1, pass 2)
  *   d_post   [2][B][n] float posteriors at the end of each pass (pass-2 rows
