@@ -49,6 +49,22 @@ def test_group_kernel_bit_exact(P, name):
     assert_bit_exact(g, ref, code.n)
 
 
+# single-code launches of small codes claim several consecutive shots at a time (toric L = 6,
+# 72 columns: 8): one shot, batches that end inside the first claim or just past it, and a batch
+# whose last claim straddles its end, all bit-exact at a nonzero shot offset
+@pytest.mark.parametrize("B", [1, 7, 8, 9, 1001])
+def test_group_kernel_claims_of_consecutive_shots(P, B):
+    code = synth.toric_code(6, p=0.07)
+    shots = synth.make_shots(code, B, 900 + B)
+    prm = P.Params(max_iter=(30, 30), alpha=0.625, second_pass_prior=P.PRIOR_POSTERIOR, seed=9)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    print(f"case group claims toric6 B={B}", flush=True)
+    g = gpu_decode(plan, code, shots.syndromes, shot_offset=1_000_003)
+    ref = oracle.decode(code, shots.syndromes, oracle_params(prm, "posterior"), precision="f32",
+                        shot_offset=1_000_003)
+    assert_bit_exact(g, ref, code.n)
+
+
 def test_auto_plan_picks_lane_for_small_and_group_for_large(P):
     prm = P.Params(max_iter=(20, 20))
     small = P.Code.from_problem(synth.bb_code("bb144"))
