@@ -611,6 +611,15 @@ WCode wcode(const DevCode& d) {
   return c;
 }
 
+// Compile-time bounds on the column and row degrees of a code's kernels (the
+// unrolled per-column and per-row loops run every slot, masked past a short
+// column or row): 3 and 6 (BB codes), 4 and 8, else 16 and the row limit.
+int wms_degree_class(const DevCode& d) {
+  if (d.max_col_deg <= 3 && d.max_row_deg <= 6) return 0;
+  if (d.max_col_deg <= 4 && d.max_row_deg <= 8) return 1;
+  return 2;
+}
+
 size_t fwd_wave_bytes(const DevCode& d) {
   return align16((size_t)(d.E + d.n) * 4 + (size_t)(((d.n + 31) / 32) + ((d.m + 31) / 32)) * 4);
 }
@@ -691,17 +700,18 @@ hipError_t wms_forward(const DevCode& d, const KParams& p, const float* w, const
   a.flags = flags;
   a.tab_bytes = fwd_tab_bytes(d);
   a.wave_bytes = fwd_wave_bytes(d);
-  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8;
-  const void* kern = small ? (const void*)k_wms_forward<4, 8> : (const void*)k_wms_forward<16, kWmsMaxRowDeg>;
+  static const void* const kerns[3] = {(const void*)k_wms_forward<3, 6>, (const void*)k_wms_forward<4, 8>,
+                                       (const void*)k_wms_forward<16, kWmsMaxRowDeg>};
+  const void* kern = kerns[wms_degree_class(d)];
   if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
   const int waves = wms_waves(a.tab_bytes, a.wave_bytes, max_lds);
   const size_t lds = a.tab_bytes + (size_t)waves * a.wave_bytes;
   (void)hipGetLastError();
   const int grid = wms_grid(kern, 64 * waves, lds, num_cu, B);
-  if (small) hipLaunchKernelGGL((k_wms_forward<4, 8>), dim3(grid), dim3(64 * waves), lds, stream, a);
-  else hipLaunchKernelGGL((k_wms_forward<16, kWmsMaxRowDeg>), dim3(grid), dim3(64 * waves), lds, stream, a);
-  return hipGetLastError();
+  void* args[] = {&a};
+  const hipError_t e = hipLaunchKernel(kern, dim3(grid), dim3(64 * waves), args, lds, stream);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, const uint64_t* syn, int64_t B, int K,
@@ -714,10 +724,11 @@ hipError_t wms_backward(const DevCode& d, const KParams& p, const float* w, cons
   a.gw = gw;
   a.tab_bytes = bwd_tab_bytes(d);
   a.wave_bytes = bwd_wave_bytes(d, K);
-  const bool small = d.max_col_deg <= 4 && d.max_row_deg <= 8, seg = K > 1;
-  const void* kern = small ? (seg ? (const void*)k_wms_backward<4, 8, true> : (const void*)k_wms_backward<4, 8, false>)
-                           : (seg ? (const void*)k_wms_backward<16, kWmsMaxRowDeg, true>
-                                  : (const void*)k_wms_backward<16, kWmsMaxRowDeg, false>);
+  static const void* const kerns[3][2] = {
+      {(const void*)k_wms_backward<3, 6, false>, (const void*)k_wms_backward<3, 6, true>},
+      {(const void*)k_wms_backward<4, 8, false>, (const void*)k_wms_backward<4, 8, true>},
+      {(const void*)k_wms_backward<16, kWmsMaxRowDeg, false>, (const void*)k_wms_backward<16, kWmsMaxRowDeg, true>}};
+  const void* kern = kerns[wms_degree_class(d)][K > 1 ? 1 : 0];
   if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess)
     return hipErrorInvalidValue;
   const int waves = wms_waves(a.tab_bytes, a.wave_bytes, max_lds);

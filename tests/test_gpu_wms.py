@@ -215,3 +215,91 @@ def test_adjoint_of_a_loss_on_the_final_row_of_every_shot(setup):
         checked[int(j >= E)] += 1
     assert checked[0] >= 12 and checked[1] >= 4, checked
     assert np.abs(gw[:E]).max() > 0
+
+
+def _balanced_code(m, R, dv, d_rows, d_weight, p, seed):
+    """Every column meets dv distinct checks of lowest current degree (rows of exactly R edges);
+    D: d_rows random column subsets of weight d_weight."""
+    n = m * R // dv
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(m, dtype=np.int64)
+    H = np.zeros((m, n), dtype=np.uint8)
+    for v in rng.permutation(n):
+        for c in np.argsort(deg * m + rng.permutation(m))[:dv]:
+            H[c, v] = 1
+            deg[c] += 1
+    D = np.zeros((d_rows, n), dtype=np.uint8)
+    for i in range(d_rows):
+        D[i, rng.choice(n, size=d_weight, replace=False)] = 1
+    return synth.Code(f"balanced_m{m}_r{R}_dv{dv}", synth.Csr.from_dense(H), synth.Csr.from_dense(D),
+                      np.full(n, p), None, "channel")
+
+
+# the weighted kernels are compiled for three degree classes (columns / rows of at most 3 / 6, the
+# BB codes above; 4 / 8; 16 / 21): an HGP code (rows of 7, columns of 3 and 4) and a synthetic code
+# with rows of 12 and columns of 5 run the other two.  Per code: (builder, iterations per pass,
+# finite-difference step).  Rows of 12 make the loss far less smooth at 15 iterations (most
+# coordinates then have a min switch within any usable step), so that code runs 6 + 6 with a
+# smaller step.
+DEGREE_CODES = {
+    "hgp_rows7": (lambda: synth.hgp_code(synth.random_regular_classical(12, 4400), name="hgp_w", p=0.05,
+                                         with_logicals=False), 15, 1e-4),
+    "rows12_cols5": (lambda: _balanced_code(60, 12, 5, 60, 6, 0.03, 4401), 6, 1e-5),
+}
+
+
+@pytest.mark.parametrize("name", list(DEGREE_CODES))
+def test_weighted_degree_classes(name):
+    import torch
+    import paper_2510_08695_amd as P
+    build, iters, step = DEGREE_CODES[name]
+    code = build()
+    prm = P.Params(max_iter=(iters, iters), alpha=0.625, stop_on_converge=False, seed=23)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    E = code.H.nnz
+    print(f"case weighted {name}: rows <= {code.H.row_weights().max()}, columns <= {code.H.col_weights().max()}",
+          flush=True)
+    rng = np.random.default_rng(5)
+    # forward: bit-exact with the float32 oracle on the same per-edge scales
+    shots = synth.make_shots(code, 200, 5101)
+    w = (0.625 + 0.1 * rng.standard_normal(2 * E)).astype(np.float32)
+    syn, wt, out = _run_fwd(plan, code, shots.syndromes, w, 1)
+    ref = oracle.decode(code, shots.syndromes, oracle_params(prm, "channel"), precision="f32",
+                        weights=w.astype(np.float64), want_post1=True)
+    post = out["post"].cpu().numpy()
+    flags = out["flags"].cpu().numpy()
+    cut = synth.unpack_bits(out["cut"].cpu().numpy().view(np.uint64), code.n)
+    np.testing.assert_array_equal(flags, ref["flags"])
+    np.testing.assert_array_equal(cut, ref["cut"])
+    np.testing.assert_array_equal(post[0].view(np.uint32), ref["post1"].astype(np.float32).view(np.uint32))
+    dc = (ref["flags"] & 2) != 0
+    assert dc.sum() > 3
+    np.testing.assert_array_equal(post[1][dc].view(np.uint32), ref["post"][dc].astype(np.float32).view(np.uint32))
+    # adjoint: central finite differences of the float64 oracle's loss (checkpoints every iteration)
+    _, gpost = _loss_and_grad_post(post, shots.errors, cut, flags)
+    gw = plan.wms_backward(wt, syn, out, torch.from_numpy(gpost.astype(np.float32)).cuda()).cpu().numpy()
+    op = oracle_params(prm, "channel")
+
+    def f64_loss(wv):
+        o = oracle.decode(code, shots.syndromes, op, precision="f64", weights=wv, want_post1=True)
+        return _loss_and_grad_post(np.stack([o["post1"], o["post"]]), shots.errors, o["cut"], o["flags"])[0], o["cut"]
+
+    w64 = w.astype(np.float64)
+    base, base_cut = f64_loss(w64)
+    checked = 0
+    for j in rng.choice(2 * E, size=32, replace=False):
+        h = step * max(1.0, abs(w64[j]))
+        wp, wm = w64.copy(), w64.copy()
+        wp[j] += h
+        wm[j] -= h
+        lp, cp = f64_loss(wp)
+        lm, cm = f64_loss(wm)
+        if not ((cp == base_cut).all() and (cm == base_cut).all()):
+            continue
+        fwd, bwd = (lp - base) / h, (base - lm) / h
+        if abs(fwd - bwd) > 1e-3 * max(1e-3, abs(fwd) + abs(bwd)):
+            continue
+        fd = (lp - lm) / (2 * h)
+        assert abs(gw[j] - fd) <= 2e-3 * max(abs(fd), 1e-3), (j, gw[j], fd)
+        checked += 1
+    assert checked >= 16, checked
