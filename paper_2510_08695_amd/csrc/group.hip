@@ -10,7 +10,8 @@
 // Per iteration (flooding schedule, Sec. II.C) it runs
 //   variable phase: one thread per column: L_v = prior + sum r (ascending
 //                  check order), +inf on cut columns (Algorithm 2);
-//   check phase  : one thread per check: q = sat(L_v - r_old) for each edge,
+//   check phase  : one thread per check: q = L_v - r_old for each edge (its
+//                  clamp to lsat would change nothing here),
 //                  new (alpha*min1, alpha*min2, argmin, r-sign bits), and the
 //                  parity of [L <= 0] over the check against the syndrome bit
 //                  (the stop test H e = s of this iteration);
@@ -113,7 +114,8 @@ struct __align__(16) CheckRec<false> {
   static __device__ __forceinline__ Word push_sign(Word sb, float q, int) {
     return __builtin_amdgcn_alignbit(sb, __float_as_uint(q), 31);  // (sb << 1) | sign(q)
   }
-  static __device__ __forceinline__ Word finish_signs(Word sb, int K) { return K > 0 ? sb << (32 - K) : 0u; }
+  // (K = 0: no position was pushed and sb is 0; the shift count is taken mod 32)
+  static __device__ __forceinline__ Word finish_signs(Word sb, int K) { return sb << ((32 - K) & 31); }
 };
 template <>
 struct __align__(16) CheckRec<true> {
@@ -187,18 +189,29 @@ __device__ __forceinline__ float col_sum(float Lv, __amdgpu_buffer_rsrc_t vt, u3
   return Lv;
 }
 
-// The first K table entries of a column and its prior (K uniform, at most 4).
-__device__ __forceinline__ void col_fetch(u32 (&e)[4], float& lam, int K, __amdgpu_buffer_rsrc_t vt,
-                                          __amdgpu_buffer_rsrc_t lt, u32 n4, u32 vo) {
-  lam = __uint_as_float(vtab_at(lt, 0u, vo));
+// Where the pipelined variable phase takes a column's prior from: the code's
+// prior table (first pass, channel prior); the same table with +inf on the
+// shot's cut columns (second pass, channel prior: Algorithm 2's frozen
+// columns); the shot's prior array in LDS (soft DC, posterior prior, whose
+// cut columns already hold +inf).
+enum PriorSrc { kPriorTable, kPriorTableCut, kPriorLds };
+
+// The K table entries of column v and its prior.
+template <int K, int Src>
+__device__ __forceinline__ void col_fetch(u32 (&e)[K], float& lam, __amdgpu_buffer_rsrc_t vt,
+                                          __amdgpu_buffer_rsrc_t lt, const float* lam2, u32 n4, int v) {
+  const u32 vo = (u32)v << 2;
+  if constexpr (Src == kPriorLds) lam = lam2[v];
+  else lam = __uint_as_float(vtab_at(lt, 0u, vo));
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (j < K) e[j] = vtab_at(vt, (u32)j * n4, vo);
+  for (int j = 0; j < K; ++j) e[j] = vtab_at(vt, (u32)j * n4, vo);
 }
 
 // L + the r of a column's K fetched entries, in slot (ascending check) order.
+// A cut column's L starts at +inf and stays there (+inf + r = +inf: r is
+// finite).
 template <int K, class Rec>
-__device__ __forceinline__ float col_add(float Lv, const u32 (&e)[4]) {
+__device__ __forceinline__ float col_add(float Lv, const u32 (&e)[K]) {
   Rec sr[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -208,6 +221,56 @@ __device__ __forceinline__ float col_add(float Lv, const u32 (&e)[4]) {
 #pragma unroll
   for (int j = 0; j < K; ++j) Lv = Lv + sr[j].r_of(e[j]);
   return Lv;
+}
+
+// A column's prior, +inf if it is this thread's i-th column and cut (bit i of
+// cutbits; sign-extended to a mask that selects the bits of +inf).
+template <int Src>
+__device__ __forceinline__ float col_prior(float lam, u32 cutbits, int i) {
+  if constexpr (Src != kPriorTableCut) return lam;
+  const u32 msk = (u32)((int)(cutbits << (31 - i)) >> 31);
+  return __uint_as_float((msk & 0x7f800000u) | (~msk & __float_as_uint(lam)));
+}
+
+// Variable phase of a code whose columns have at most K table entries (K =
+// the code's largest column degree; shorter columns are padded with the dummy
+// check, whose r is -0): thread tid takes columns tid, tid + nt, ...; the next
+// column's entries and prior are loaded while this column's check records are
+// read and summed (the same sums in the same order).  Two register sets take
+// turns, so nothing is copied between columns, and the prefetch index is
+// clamped to the last column, so every load is in bounds.
+template <int K, class Rec, int Src>
+__device__ __forceinline__ void var_phase(float* L, const float* lam2, int n, int tid, int nt, u32 cutbits,
+                                          __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
+  if (tid >= n) return;
+  const int last = n - 1;
+  u32 ea[K], eb[K];
+  float la, lb;
+  int v = tid;
+  col_fetch<K, Src>(ea, la, vt, lt, lam2, n4, v);
+  for (int i = 0;; i += 2) {
+    col_fetch<K, Src>(eb, lb, vt, lt, lam2, n4, min(v + nt, last));
+    L[v] = col_add<K, Rec>(col_prior<Src>(la, cutbits, i), ea);
+    v += nt;
+    if (v >= n) break;
+    col_fetch<K, Src>(ea, la, vt, lt, lam2, n4, min(v + nt, last));
+    L[v] = col_add<K, Rec>(col_prior<Src>(lb, cutbits, i + 1), eb);
+    v += nt;
+    if (v >= n) break;
+  }
+}
+
+// var_phase for the code's largest column degree K (uniform, 1 to 4).
+template <class Rec, int Src>
+__device__ __forceinline__ void var_phase_k(int K, float* L, const float* lam2, int n, int tid, int nt, u32 cutbits,
+                                            __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
+  switch (K) {
+    case 1: var_phase<1, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
+    case 2: var_phase<2, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
+    case 3: var_phase<3, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
+    case 4: var_phase<4, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
+    default: break;
+  }
 }
 
 // Running state of a check over its row: min1, min2 and argmin of |q|, the
@@ -220,17 +283,20 @@ struct RowAcc {
   u64 pm;
 };
 
-// K consecutive row slots (from k0) of a check: q = sat(L - r_old) in row
-// order, all loads issued before the updates.  r_old is alpha * (min2 on the
-// old argmin, min1 elsewhere) with its sign bit (the magnitude is +0 or
-// positive, alpha >= 0, or -0 on the dummy check, whose sign bits are 0).  A
-// posterior is never -0 (it starts from a prior that is not -0 and adds
-// messages; x + y is -0 only when both are), so q is never -0 and its sign bit
-// is [q < 0]; the hard-decision parity takes one wave-wide compare per edge,
-// the xor on the scalar unit.
+// K consecutive row slots (from k0) of a check: q = L - r_old in row order,
+// all loads issued before the updates.  r_old is alpha * (min2 on the old
+// argmin, min1 elsewhere) with its sign bit (the magnitude is +0 or positive,
+// alpha >= 0, or -0 on the dummy check, whose sign bits are 0).  q is not
+// clamped to +-lsat: it enters the state only through its sign, which the
+// clamp keeps, and through min / median operations against minima that start
+// at lsat, which a |q| above lsat leaves as lsat itself would (+inf from a cut
+// or dummy column included: r is finite).  A posterior is never -0 (it starts
+// from a prior that is not -0 and adds messages; x + y is -0 only when both
+// are), so q is never -0 and its sign bit is [q < 0]; the hard-decision parity
+// takes one wave-wide compare per edge, the xor on the scalar unit.
 template <int K, class Rec>
 __device__ __forceinline__ void row_chunk(RowAcc<Rec>& a, const Rec& so, typename Rec::Word io, int am_old, int k0,
-                                          __amdgpu_buffer_rsrc_t ct, u32 m4, u32 co, float LS) {
+                                          __amdgpu_buffer_rsrc_t ct, u32 m4, u32 co) {
   u32 lo[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) lo[j] = vtab_at(ct, (u32)(k0 + j) * m4, co);
@@ -245,7 +311,7 @@ __device__ __forceinline__ void row_chunk(RowAcc<Rec>& a, const Rec& so, typenam
     a.pm ^= __ballot(Lv <= 0.0f);
     const float mag = (am_old == k) ? so.a2 : so.a1;
     const float r = __uint_as_float(Rec::old_sign(io, k) | __float_as_uint(mag));
-    const float q = bpdc_dev::sat(Lv - r, LS);
+    const float q = Lv - r;
     const float aq = fabsf(q);
     const bool lt = aq < a.m1;
     amj = lt ? j : amj;
@@ -254,6 +320,34 @@ __device__ __forceinline__ void row_chunk(RowAcc<Rec>& a, const Rec& so, typenam
     a.sb = Rec::push_sign(a.sb, q, k);
   }
   a.amin = (amj >= 0) ? k0 + amj : a.amin;
+}
+
+// A whole row of K <= 8 slots as one chunk from position 0 (the same
+// operations as row_chunk): the positions are constants, so the old-argmin
+// test and the sign shift take inline constants and the new argmin is kept
+// directly.
+template <int K, class Rec>
+__device__ __forceinline__ void row_whole(RowAcc<Rec>& a, const Rec& so, typename Rec::Word io, int am_old,
+                                          __amdgpu_buffer_rsrc_t ct, u32 m4, u32 co) {
+  u32 lo[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) lo[j] = vtab_at(ct, (u32)j * m4, co);
+  float Lj[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) Lj[j] = *lds_at<float>(lo[j]);
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const float Lv = Lj[j];
+    a.pm ^= __ballot(Lv <= 0.0f);
+    const float mag = (am_old == j) ? so.a2 : so.a1;
+    const float q = Lv - __uint_as_float(Rec::old_sign(io, j) | __float_as_uint(mag));
+    const float aq = fabsf(q);
+    const bool lt = aq < a.m1;
+    a.amin = lt ? j : a.amin;
+    a.m2 = __builtin_amdgcn_fmed3f(aq, a.m1, a.m2);
+    a.m1 = lt ? aq : a.m1;
+    a.sb = Rec::push_sign(a.sb, q, j);
+  }
 }
 __device__ __forceinline__ float gloadf(const float* p, unsigned i) {
   return ((const __attribute__((address_space(1))) float*)p)[i];
@@ -388,6 +482,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       // chunks by its block's largest degree; the 32-bit variant keeps the
       // code's (fewer registers live)
       const bool blk_deg = Wide && (nt & 63) == 0;
+      // the pipelined variable phase takes narrow-record min-sum codes whose
+      // columns have 1 to 4 table entries
+      const bool fast_cols = !Wide && !PS && C.max_col_deg >= 1 && C.max_col_deg <= 4;
       // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
       // padded row entry reads L = +inf, so q saturates at lsat: it is never a
       // new minimum, leaves the second minimum (a median with lsat) and the
@@ -411,6 +508,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       for (int pass = 0; pass < 2; ++pass) {
         const int T = pass ? P.T2 : P.T1;
         const bool use_lam2 = (pass == 1 && P.second_pass_posterior) || (pass == 0 && soft);
+        // the second pass under the channel prior keeps this thread's cut
+        // columns as bits of a register (column tid + i nt at bit i), so the
+        // pipelined variable phase needs at most 32 columns per thread
+        const bool fast_var = fast_cols && (pass == 0 || use_lam2 || n <= 32 * nt);
+        u32 cutbits = 0u;
+        if (pass == 1 && fast_var && !use_lam2)
+          for (int v = tid, i = 0; v < n; v += nt, ++i) cutbits |= ((cutw[v >> 5] >> (v & 31)) & 1u) << i;
         if (PS)
           for (int e = tid; e < E; e += nt) R[e] = 0.0f;
         else
@@ -424,28 +528,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           // Only the second pass has cut columns (+inf: with the posterior prior
           // lam2 holds them); the first pass's priors are finite.
           const bool cuts = pass == 1;
-          if (!PS && !use_lam2 && !cuts && !blk_deg && C.max_col_deg <= 4) {
-            // first pass (no cut columns, the channel prior), columns of at most
-            // 4 entries: software-pipelined, the next column's table entries and
-            // prior are in flight while this column's check records are read
-            // and summed (the same sums in the same order)
-            const int K = C.max_col_deg;
-            u32 e[4] = {0u, 0u, 0u, 0u};
-            float lam = 0.0f;
-            if (tid < n) col_fetch(e, lam, K, vt, lt, n4, (u32)tid << 2);
-            for (int v = tid; v < n; v += nt) {
-              const u32 ce[4] = {e[0], e[1], e[2], e[3]};
-              float Lv = lam;
-              if (v + nt < n) col_fetch(e, lam, K, vt, lt, n4, (u32)(v + nt) << 2);
-              switch (K) {  // uniform
-                case 4: Lv = col_add<4, Rec>(Lv, ce); break;
-                case 3: Lv = col_add<3, Rec>(Lv, ce); break;
-                case 2: Lv = col_add<2, Rec>(Lv, ce); break;
-                case 1: Lv = col_add<1, Rec>(Lv, ce); break;
-                default: break;
-              }
-              L[v] = Lv;
-            }
+          if (fast_var) {
+            // narrow records, columns of 1 to 4 entries: the pipelined phase
+            const int Kc = C.max_col_deg;
+            if (use_lam2) var_phase_k<Rec, kPriorLds>(Kc, L, lam2, n, tid, nt, 0u, vt, lt, n4);
+            else if (cuts) var_phase_k<Rec, kPriorTableCut>(Kc, L, lam2, n, tid, nt, cutbits, vt, lt, n4);
+            else var_phase_k<Rec, kPriorTable>(Kc, L, lam2, n, tid, nt, 0u, vt, lt, n4);
           } else
           for (int v = tid; v < n; v += nt) {
             const u32 vo = (u32)v << 2;
@@ -475,7 +563,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           }
           if (tid == 0) sUnsat[t & 1] = 0;
           __syncthreads();
-          // ---- check phase: next check state from q = sat(L - r_old), with the stop
+          // ---- check phase: next check state from q = L - r_old, with the stop
           // test H e = s (e = [L <= 0]) on the way; the new state is not used
           // when the pass ends here ----
           int bad = 0;
@@ -525,11 +613,28 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             const u32 co = (u32)c << 2;
             const W io = so.signs();
             const int am_old = so.argmin(), K = C.max_row_deg;
-            int k0 = 0;
-            for (; k0 + 8 <= K; k0 += 8) row_chunk<8, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
-            if ((K - k0) & 4) { row_chunk<4, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 4; }
-            if ((K - k0) & 2) { row_chunk<2, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS); k0 += 2; }
-            if ((K - k0) & 1) row_chunk<1, Rec>(acc, so, io, am_old, k0, ct, m4, co, LS);
+            bool whole = false;
+            if constexpr (!Wide) {
+              whole = K <= 8;
+              switch (K) {  // uniform
+                case 8: row_whole<8, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 7: row_whole<7, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 6: row_whole<6, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 5: row_whole<5, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 4: row_whole<4, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 3: row_whole<3, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 2: row_whole<2, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                case 1: row_whole<1, Rec>(acc, so, io, am_old, ct, m4, co); break;
+                default: break;
+              }
+            }
+            if (!whole) {
+              int k0 = 0;
+              for (; k0 + 8 <= K; k0 += 8) row_chunk<8, Rec>(acc, so, io, am_old, k0, ct, m4, co);
+              if ((K - k0) & 4) { row_chunk<4, Rec>(acc, so, io, am_old, k0, ct, m4, co); k0 += 4; }
+              if ((K - k0) & 2) { row_chunk<2, Rec>(acc, so, io, am_old, k0, ct, m4, co); k0 += 2; }
+              if ((K - k0) & 1) row_chunk<1, Rec>(acc, so, io, am_old, k0, ct, m4, co);
+            }
             const W sb = Rec::finish_signs(acc.sb, K);
             const float m1 = acc.m1, m2 = acc.m2;
             const int amin = acc.amin;
