@@ -500,6 +500,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         synw[w] = (w & 1) ? (u32)(x >> 32) : (u32)x;
       }
       for (int w = tid; w < ((n + 31) >> 5); w += nt) cutw[w] = 0u;
+      // the syndrome bits of this thread's checks (check tid + k nt at bit k)
+      // in a register when they fit (every code the LDS holds, with 1024
+      // threads); otherwise the check phase reads them from LDS
+      const bool reg_syn = m <= 32 * nt;
+      u32 synbits = 0u;
+      if (reg_syn)
+        for (int c = tid, k = 0; c < m; c += nt, ++k) synbits |= (u32)((sp[c >> 6] >> (c & 63)) & 1u) << k;
 
       // iterations of each pass (scalars, not an array indexed by the pass: that
       // would live in per-thread scratch memory)
@@ -603,7 +610,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
               bad |= (int)par;
             }
           } else
-          for (int c = tid; c < m; c += nt) {
+          for (int c = tid, k = 0; c < m; c += nt, ++k) {
             const Rec so = S[c];
             RowAcc<Rec> acc{LS, LS, 0, 0, 0u};
             // the check table holds the LDS address of each entry's L; the
@@ -638,15 +645,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             const W sb = Rec::finish_signs(acc.sb, K);
             const float m1 = acc.m1, m2 = acc.m2;
             const int amin = acc.amin;
-            const u32 par = ((u32)(acc.pm >> lane) & 1u) ^ ((synw[c >> 5] >> (c & 31)) & 1u);
-            bad |= (int)par;
-            const u32 rp = ((u32)popc_word(sb) ^ ((synw[c >> 5] >> (c & 31)) & 1u)) & 1u;
+            u32 sbit;
+            if (reg_syn) sbit = (synbits >> k) & 1u;
+            else sbit = (synw[c >> 5] >> (c & 31)) & 1u;
+            // stop test on the wave's checks (a prefix of its lanes is active,
+            // lane 0 among them): hard-decision parity against the syndrome
+            // (a plain store of 1: every writer stores the same value)
+            if ((acc.pm ^ __ballot(sbit != 0u)) != 0ull && lane == 0)
+              __hip_atomic_store(&sUnsat[t & 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // parity of the q signs and the syndrome bit: bit 0 of their sum
+            const u32 rp = ((u32)popc_word(sb) + sbit) & 1u;
             // flip every sign bit on an odd parity: the bits past the row's
             // degree are read only by padding entries, whose q saturates anyway
             const W rb = rp ? (sb ^ Rec::kSignMask) : sb;
             S[c].set(P.alpha * m1, P.alpha * m2, rb, amin, c + kRec0);
           }
-          if (__ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
+          if (PS && __ballot(bad) != 0ull && lane == 0) atomicOr(&sUnsat[t & 1], 1);
           __syncthreads();
           if (t >= 1) {
             const bool ok = sUnsat[t & 1] == 0;
