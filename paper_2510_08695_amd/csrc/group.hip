@@ -41,12 +41,18 @@ struct GCode {
   const int32_t* d_row_ptr;
   const int32_t* d_col;
   const float* lam;
-  const int32_t* v_ell;  // [max_col_deg][n]: (check << 6) | position in the check's row, ascending checks;
-                         // padded with check m (a dummy whose messages are -0)
-  const int32_t* c_ell;  // [max_row_deg][m]: column at each position of the check's row; padded with column n
-                         // (a dummy whose posterior is +inf)
-  const int32_t* v_blk_deg;  // [ceil(n/64)]: largest column degree of each block of 64 columns
+  // Min-sum keeps L in slot order: for codes with rows above 32 edges the
+  // columns sorted by descending degree (ties in column order), otherwise the
+  // column order.
+  const int32_t* v_ell;  // [max_col_deg][n]: per slot, ((check + kRec0) << 10) | position in the check's
+                         // row, ascending checks; padded with check m (a dummy whose messages are -0)
+  const int32_t* c_ell;  // [max_row_deg][m]: LDS address of L at each position of the check's row; padded
+                         // with slot n (a dummy whose posterior is +inf)
+  const int32_t* v_blk_deg;  // [ceil(n/64)]: largest column degree of each block of 64 slots
   int max_col_deg, max_row_deg;
+  const float* g_lam;     // [n] prior of each slot
+  const int32_t* g_dcol;  // rows of D as slots (each row in ascending column order)
+  const int32_t* g_pos;   // [n] slot of each column
 };
 
 namespace {
@@ -232,44 +238,58 @@ __device__ __forceinline__ float col_prior(float lam, u32 cutbits, int i) {
   return __uint_as_float((msk & 0x7f800000u) | (~msk & __float_as_uint(lam)));
 }
 
-// Variable phase of a code whose columns have at most K table entries (K =
-// the code's largest column degree; shorter columns are padded with the dummy
-// check, whose r is -0): thread tid takes columns tid, tid + nt, ...; the next
-// column's entries and prior are loaded while this column's check records are
-// read and summed (the same sums in the same order).  Two register sets take
-// turns, so nothing is copied between columns, and the prefetch index is
-// clamped to the last column, so every load is in bounds.
+// Variable phase over the run of slots [s0, s1), whose columns all have K
+// table entries: thread tid takes slots s0 + tid, s0 + tid + nt, ...; the next
+// slot's entries and prior are loaded while this slot's check records are read
+// and summed (the same sums in the same order).  Two register sets take turns,
+// so nothing is copied between slots, and the prefetch index is clamped to
+// the run's last slot, so every load is in bounds.  i counts the thread's
+// slots over the whole phase (the cut bit of each); the count after the run
+// is returned.
 template <int K, class Rec, int Src>
-__device__ __forceinline__ void var_phase(float* L, const float* lam2, int n, int tid, int nt, u32 cutbits,
-                                          __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
-  if (tid >= n) return;
-  const int last = n - 1;
+__device__ __forceinline__ int var_run(float* L, const float* lam2, int s0, int s1, int tid, int nt, u32 cutbits,
+                                       int i, __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
+  int v = s0 + tid;
+  if (v >= s1) return i;
+  const int last = s1 - 1;
   u32 ea[K], eb[K];
   float la, lb;
-  int v = tid;
   col_fetch<K, Src>(ea, la, vt, lt, lam2, n4, v);
-  for (int i = 0;; i += 2) {
+  for (;;) {
     col_fetch<K, Src>(eb, lb, vt, lt, lam2, n4, min(v + nt, last));
-    L[v] = col_add<K, Rec>(col_prior<Src>(la, cutbits, i), ea);
+    L[v] = col_add<K, Rec>(col_prior<Src>(la, cutbits, i++), ea);
     v += nt;
-    if (v >= n) break;
+    if (v >= s1) break;
     col_fetch<K, Src>(ea, la, vt, lt, lam2, n4, min(v + nt, last));
-    L[v] = col_add<K, Rec>(col_prior<Src>(lb, cutbits, i + 1), eb);
+    L[v] = col_add<K, Rec>(col_prior<Src>(lb, cutbits, i++), eb);
     v += nt;
-    if (v >= n) break;
+    if (v >= s1) break;
   }
+  return i;
 }
 
-// var_phase for the code's largest column degree K (uniform, 1 to 4).
+// Variable phase of a code whose columns have at most K <= 4 entries (K = the
+// code's largest column degree, uniform; shorter columns are padded with the
+// dummy check, whose r is -0), all slots as one run.  (Runs of one degree
+// each, without padding, were measured slower: every run starts with its
+// loads exposed.)
 template <class Rec, int Src>
-__device__ __forceinline__ void var_phase_k(int K, float* L, const float* lam2, int n, int tid, int nt, u32 cutbits,
-                                            __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
+__device__ __forceinline__ void var_phase(int K, int n, float* L, const float* lam2, int tid, int nt, u32 cutbits,
+                                          __amdgpu_buffer_rsrc_t vt, __amdgpu_buffer_rsrc_t lt, u32 n4) {
   switch (K) {
-    case 1: var_phase<1, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
-    case 2: var_phase<2, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
-    case 3: var_phase<3, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
-    case 4: var_phase<4, Rec, Src>(L, lam2, n, tid, nt, cutbits, vt, lt, n4); break;
-    default: break;
+    case 4: var_run<4, Rec, Src>(L, lam2, 0, n, tid, nt, cutbits, 0, vt, lt, n4); break;
+    case 3: var_run<3, Rec, Src>(L, lam2, 0, n, tid, nt, cutbits, 0, vt, lt, n4); break;
+    case 2: var_run<2, Rec, Src>(L, lam2, 0, n, tid, nt, cutbits, 0, vt, lt, n4); break;
+    case 1: var_run<1, Rec, Src>(L, lam2, 0, n, tid, nt, cutbits, 0, vt, lt, n4); break;
+    default: {
+      int i = 0;
+      for (int v = tid; v < n; v += nt) {  // no column has a check: L = prior
+        float lam;
+        if constexpr (Src == kPriorLds) lam = lam2[v];
+        else lam = __uint_as_float(vtab_at(lt, 0u, (u32)v << 2));
+        L[v] = col_prior<Src>(lam, cutbits, i++);
+      }
+    }
   }
 }
 
@@ -378,7 +398,15 @@ __device__ __forceinline__ GCode uniform_code(const GCode* codes, int ci) {
   c.d_row_ptr = uniform(c.d_row_ptr); c.d_col = uniform(c.d_col); c.lam = uniform(c.lam);
   c.v_ell = uniform(c.v_ell); c.c_ell = uniform(c.c_ell); c.v_blk_deg = uniform(c.v_blk_deg);
   c.max_col_deg = uniform(c.max_col_deg); c.max_row_deg = uniform(c.max_row_deg);
+  c.g_lam = uniform(c.g_lam);
   return c;
+}
+
+// A field of a code description read again where it is used (a volatile
+// load, so that it does not occupy registers for the rest of the shot).
+template <class T>
+__device__ __forceinline__ T code_field(const T* p) {
+  return uniform(*(const volatile T*)p);
 }
 
 // DC nomination of one row of D (the rule of bpdc_device.h's dc_pick, in the
@@ -466,7 +494,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       const int E = PS ? C.h_row_ptr[m] : 0;
       unsigned char* state = smem + kLdsHead;
       const __amdgpu_buffer_rsrc_t vt = table_rsrc(C.v_ell), ct = table_rsrc(C.c_ell),
-                                   lt = table_rsrc((const int32_t*)C.lam);
+                                   lt = table_rsrc((const int32_t*)(PS ? C.lam : C.g_lam));
       const u32 n4 = (u32)n * 4u, m4 = (u32)m * 4u;
       Rec* S = (Rec*)state;                          // [m + 1] check states (min-sum)
       float* R = (float*)state;                      // [E] per-edge r (product-sum)
@@ -484,7 +512,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       const bool blk_deg = Wide && (nt & 63) == 0;
       // the pipelined variable phase takes narrow-record min-sum codes whose
       // columns have 1 to 4 table entries
-      const bool fast_cols = !Wide && !PS && C.max_col_deg >= 1 && C.max_col_deg <= 4;
+      const bool fast_cols = !Wide && !PS && C.max_col_deg <= 4;
       // dummies: a padded column entry adds r = -0 (x + -0 = x for every x), a
       // padded row entry reads L = +inf, so q saturates at lsat: it is never a
       // new minimum, leaves the second minimum (a median with lsat) and the
@@ -518,6 +546,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         // the second pass under the channel prior keeps this thread's cut
         // columns as bits of a register (column tid + i nt at bit i), so the
         // pipelined variable phase needs at most 32 columns per thread
+        // (slot tid + i nt at bit i: at most 32 slots per thread)
         const bool fast_var = fast_cols && (pass == 0 || use_lam2 || n <= 32 * nt);
         u32 cutbits = 0u;
         if (pass == 1 && fast_var && !use_lam2)
@@ -527,7 +556,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         else
           for (int c = tid; c < m; c += nt) S[c].set(0.0f, 0.0f, 0, 0, c + kRec0);
         if (pass == 0 && soft)
-          for (int v = tid; v < n; v += nt) lam2[v] = C.lam[v];
+          for (int v = tid; v < n; v += nt) lam2[v] = (PS ? C.lam : code_field(&a.codes[ci].g_lam))[v];
         __syncthreads();
         int t = 0;
         for (;;) {
@@ -536,11 +565,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           // lam2 holds them); the first pass's priors are finite.
           const bool cuts = pass == 1;
           if (fast_var) {
-            // narrow records, columns of 1 to 4 entries: the pipelined phase
+            // narrow records, columns of at most 4 entries: the pipelined phase
             const int Kc = C.max_col_deg;
-            if (use_lam2) var_phase_k<Rec, kPriorLds>(Kc, L, lam2, n, tid, nt, 0u, vt, lt, n4);
-            else if (cuts) var_phase_k<Rec, kPriorTableCut>(Kc, L, lam2, n, tid, nt, cutbits, vt, lt, n4);
-            else var_phase_k<Rec, kPriorTable>(Kc, L, lam2, n, tid, nt, 0u, vt, lt, n4);
+            if (use_lam2) var_phase<Rec, kPriorLds>(Kc, n, L, lam2, tid, nt, 0u, vt, lt, n4);
+            else if (cuts) var_phase<Rec, kPriorTableCut>(Kc, n, L, lam2, tid, nt, cutbits, vt, lt, n4);
+            else var_phase<Rec, kPriorTable>(Kc, n, L, lam2, tid, nt, 0u, vt, lt, n4);
           } else
           for (int v = tid; v < n; v += nt) {
             const u32 vo = (u32)v << 2;
@@ -680,7 +709,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
                 if (deg == 0) continue;
                 int unused_bin = 0;
-                const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+                const int pick = dc_pick_row(PS ? C.d_col : code_field(&a.codes[ci].g_dcol), e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
                                              (u64)(a.shot_offset + b), rbase + (u64)h, false, unused_bin);
                 atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
               }
@@ -714,7 +743,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
           const int e0 = C.d_row_ptr[h], deg = C.d_row_ptr[h + 1] - e0;
           if (deg == 0) continue;
           int bin = 0;
-          const int pick = dc_pick_row(C.d_col, e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
+          const int pick = dc_pick_row(PS ? C.d_col : code_field(&a.codes[ci].g_dcol), e0, deg, L, LS, P.tie_eps, P.tie_lowest, P.seed,
                                        (u64)(a.shot_offset + b), (u64)h, dcs, bin);
           atomicOr(&cutw[pick >> 5], 1u << (pick & 31));
           if (lds_hist) atomicAdd(&hist[bin], 1u);
@@ -741,19 +770,22 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
       // ---- outputs ----
       const bool dc = it1 > 0;
       uint64_t* cp = a.corr + (a.corr_off ? a.corr_off[b] : b * nw64);
+      // (column v's posterior and cut bit sit at its slot: v itself for
+      // product-sum)
+      const int32_t* gpos = PS ? nullptr : code_field(&a.codes[ci].g_pos);
       for (int w = wave; w < nw64; w += nwaves) {
         const int v = w * 64 + lane;
-        const u64 word = __ballot(v < n && L[v] <= 0.0f);
+        const int sv = v < n ? (PS ? v : gload(gpos, (unsigned)v)) : n;
+        const u64 word = __ballot(v < n && L[sv] <= 0.0f);
         if (lane == 0) cp[w] = word;
         if (a.cut) {
-          const u32 lo = cutw[2 * w];
-          const u32 hi = (2 * w + 1 < ((n + 31) >> 5)) ? cutw[2 * w + 1] : 0u;
-          if (lane == 0) a.cut[b * nw64 + w] = dc ? (((u64)hi << 32) | lo) : 0ull;
+          const u64 cw = __ballot(dc && v < n && ((cutw[sv >> 5] >> (sv & 31)) & 1u));
+          if (lane == 0) a.cut[b * nw64 + w] = cw;
         }
       }
       if (a.post)
         for (int v = tid; v < n; v += nt) {
-          const float x = L[v];
+          const float x = L[PS ? v : gload(gpos, (unsigned)v)];
           a.post[b * n + v] = (x == INF) ? x : bpdc_dev::sat(x, LS);
         }
       if (tid == 0) {

@@ -31,11 +31,18 @@ struct DevCode {
   // The group kernel's min-sum phases read these two tables as LDS addresses
   // (its layout: kLdsHead bytes of control words, m + 1 check records of 16
   // bytes, then L[n + 1]).
+  // The group kernel's min-sum variants keep L in slot order (for codes with
+  // rows above 32 edges the columns sorted by descending degree, ties in
+  // column order, so that a block of 64 slots mostly holds one degree;
+  // otherwise the column order) and index these by slot.
   int32_t* v_ell = nullptr;      // [max_col_deg][n] ((row + kLdsHead / 16) << 10) | position in row, ascending
                                  // rows: >> 6 is the LDS address of the row's record; pad row m
-  int32_t* c_ell = nullptr;      // [max_row_deg][m] LDS address of L[column] at each row position
-                                 // (kLdsHead + 16 (m + 1) + 4 column); pad column n
-  int32_t* v_blk_deg = nullptr;  // [ceil(n/64)] largest column degree of each block of 64 columns
+  int32_t* c_ell = nullptr;      // [max_row_deg][m] LDS address of L[slot of the column] at each row
+                                 // position (kLdsHead + 16 (m + 1) + 4 slot); pad slot n
+  int32_t* v_blk_deg = nullptr;  // [ceil(n/64)] largest column degree of each block of 64 slots
+  float* g_lam = nullptr;        // [n] prior of each slot
+  int32_t* g_dcol = nullptr;     // [dnnz] d_col as slots (rows keep ascending column order)
+  int32_t* g_pos = nullptr;      // [n] slot of each column
 };
 
 // Runtime decoder parameters as the kernels see them.
@@ -120,6 +127,9 @@ struct GCodeHost {
   const int32_t* c_ell;
   const int32_t* v_blk_deg;
   int max_col_deg, max_row_deg;
+  const float* g_lam;
+  const int32_t* g_dcol;
+  const int32_t* g_pos;
 };
 
 // Weighted min-sum forward (checkpointed) and adjoint (wms.hip).  Rows of at

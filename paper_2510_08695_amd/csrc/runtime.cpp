@@ -480,15 +480,27 @@ struct TuneBuffers {
 };
 
 // Time one decode of the synthetic batch with the given group tile (ms), or a
-// negative value if it cannot run.
-float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, TuneBuffers& tb, int S) {
+// negative value if it cannot run.  fixed: every shot runs the same number
+// of iterations per pass (no early stop, at most 16), the batch that ranks
+// thread counts: with the plan's own iteration limits the few shots of a
+// short batch that need DC and up to T1 + T2 iterations make the time the
+// latency of one shot instead of the throughput being tuned (such a batch of
+// the phenomenological DEM ranked 512 threads above 1024, which decode the
+// full workload faster).
+float time_group(const bpdc_plan_s* p, int code, const bpdc::GroupTile& tile, TuneBuffers& tb, int S, bool fixed) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0f;
   const char* tab = (const char*)p->d_code_table + (size_t)code * sizeof(bpdc::GCodeHost);
+  bpdc::KParams kt = p->kp;
+  if (fixed) {
+    kt.stop = 0;
+    kt.T1 = std::min(kt.T1, 16);
+    kt.T2 = std::min(kt.T2, 16);
+  }
   float best = -1.0f;
   for (int rep = 0; rep < 2; ++rep) {
     (void)hipEventRecord(e0, 0);
-    hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, nullptr, p->kp, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
+    hipError_t e = bpdc::group_launch(tab, nullptr, nullptr, nullptr, kt, tb.syn, nullptr, tb.corr, nullptr, tb.flags,
                                       nullptr, nullptr, nullptr, S, 0, tile.threads, tile.grid, tile.lds_bytes,
                                       tile.info_bytes, tb.queue, 0, nullptr, p->codes[code]->g.n);
     (void)hipEventRecord(e1, 0);
@@ -514,8 +526,7 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   base.lds_bytes = bpdc::group_lds_bytes_nm(d.n, d.m, group_prior_array(p), base.info_bytes, d.E);
   // powers of two (thread counts that split a phase into whole rounds, such
   // as 896 for 2592 checks, measured slower than 1024 on every code tried:
-  // fewer waves hide less latency; and their timings on a short synthetic
-  // batch, whose few long DC shots dominate it, are too close to rank)
+  // fewer waves hide less latency)
   std::vector<int> cands;
   const int work = std::max(d.n, d.m);
   for (int t : {64, 128, 256, 512, 1024}) {
@@ -554,11 +565,12 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
   for (int th : cands) {
     bpdc::GroupTile t = make(th);
     if (bpdc::group_occupancy(th, t.lds_bytes, t.info_bytes, p->max_lds) < 1) continue;
-    const float ms = time_group(p, code, t, tb, S);
+    const float ms = time_group(p, code, t, tb, S, true);
     if (tried) {
       TuneTry tt;
       tt.what = "group " + std::to_string(th) + " threads, 1 shot/workgroup, " + std::to_string(t.lds_bytes) +
-                " B LDS per shot, " + std::to_string(t.grid / p->num_cu) + " workgroups/CU";
+                " B LDS per shot, " + std::to_string(t.grid / p->num_cu) +
+                " workgroups/CU (16 + 16 iterations, no early stop)";
       tt.ms_per_kshot = ms > 0 ? ms * 1000.0 / S : -1.0;
       tried->push_back(tt);
     }
@@ -567,10 +579,21 @@ bpdc_status choose_group_tile(bpdc_plan_s* p, int code, bool autotune, bpdc::Gro
       *out = t;
     }
   }
-  if (best_ms_per_kshot) *best_ms_per_kshot = best > 0 ? best * 1000.0 / S : -1.0;
   if (best < 0)
     return fail(BPDC_ERR_UNSUPPORTED, "no group tile could run code %d (lds %zu of %d bytes, last HIP error: %s)",
                 code, base.lds_bytes, p->max_lds, hipGetErrorString(hipGetLastError()));
+  if (best_ms_per_kshot) {
+    // the chosen tile on the same batch with the plan's own iterations: the
+    // figure AUTO compares with the lane kernel's
+    const float ms = time_group(p, code, *out, tb, S, false);
+    *best_ms_per_kshot = ms > 0 ? ms * 1000.0 / S : -1.0;
+    if (tried) {
+      TuneTry tt;
+      tt.what = "group " + std::to_string(out->threads) + " threads as chosen, the plan's iterations";
+      tt.ms_per_kshot = *best_ms_per_kshot;
+      tried->push_back(tt);
+    }
+  }
   if (best_ms_out) *best_ms_out = best;
   return BPDC_OK;
 }
@@ -715,7 +738,8 @@ bpdc_status build_code_table(bpdc_plan_s* p) {
   for (size_t i = 0; i < p->codes.size(); ++i) {
     const bpdc::DevCode& d = p->codes[i]->dev;
     tab[i] = {d.n, d.m, d.md, p->kp.second_pass_posterior, d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge,
-              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam, d.v_ell, d.c_ell, d.v_blk_deg, d.max_col_deg, d.max_row_deg};
+              d.h_edge_row, d.d_row_ptr, d.d_col, d.lam, d.v_ell, d.c_ell, d.v_blk_deg, d.max_col_deg, d.max_row_deg,
+              d.g_lam, d.g_dcol, d.g_pos};
     rank[i] = (int32_t)i;
   }
   std::stable_sort(rank.begin(), rank.end(),
@@ -933,14 +957,37 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
     }
   }
   std::vector<int32_t> drp(D->row_ptr, D->row_ptr + D->rows + 1), dci(D->col_idx, D->col_idx + d.dnnz);
-  // padded column-major adjacency for the group kernel (one coalesced load per
-  // edge), in the forms its min-sum phases use directly: a column's entry is
+  // The group kernel's min-sum variants keep the posteriors in LDS in slot
+  // order.  For codes with rows above 32 edges (the 64-bit-record variant)
+  // that is the columns sorted by descending degree (ties in column order),
+  // so that a block of 64 slots mostly holds columns of one degree and the
+  // variant's per-block degree bound (each wave's variable phase stops at its
+  // block's largest degree) wastes little on padding: circuit-level BB144
+  // DEM 215 -> 211 ms.  Other codes keep the column order (the 32-bit variant
+  // runs every column to the code's largest degree, and the sorted order
+  // measured 1-2 % slower there).  g_lam holds the priors and g_dcol the rows
+  // of D in slot terms (each row's entries still in ascending column order,
+  // the order of DC's tie draw); g_pos maps a column to its slot for the
+  // outputs.
+  std::vector<int32_t> slot_col(g.n), col_slot(g.n);
+  for (int v = 0; v < g.n; ++v) slot_col[v] = v;
+  if (code_info_bytes(d) == 8)
+    std::stable_sort(slot_col.begin(), slot_col.end(),
+                     [&](int a, int b) { return cp[a + 1] - cp[a] > cp[b + 1] - cp[b]; });
+  for (int q = 0; q < g.n; ++q) col_slot[slot_col[q]] = q;
+  std::vector<float> glam(g.n);
+  for (int q = 0; q < g.n; ++q) glam[q] = c->lam[slot_col[q]];
+  std::vector<int32_t> gdcol(dci.size());
+  for (size_t k = 0; k < dci.size(); ++k) gdcol[k] = col_slot[dci[k]];
+  // padded slot-major adjacency for the group kernel (one coalesced load per
+  // edge), in the forms its min-sum phases use directly: a slot's entry is
   // ((check + kLdsHead / 16) << 10) | position in the check's row (>> 6: the LDS address
   // of the check's 16-byte record, after kLdsHead bytes of control words), a
-  // check's entry the LDS address of the column's posterior, which follows
-  // the m + 1 records.  Padding: check m / column n, dummies that the group
-  // kernel keeps in LDS.  (Codes too large for one workgroup's LDS never run
-  // the group kernel; their entries wrap harmlessly in unsigned arithmetic.)
+  // check's entry the LDS address of its column's posterior (at the column's
+  // slot), which follows the m + 1 records.  Padding: check m / slot n,
+  // dummies that the group kernel keeps in LDS.  (Codes too large for one
+  // workgroup's LDS never run the group kernel; their entries wrap harmlessly
+  // in unsigned arithmetic.)
   static_assert(bpdc::kLdsHead % 16 == 0, "check records are 16-byte aligned");
   const uint32_t rec0 = bpdc::kLdsHead / 16, l_off = (uint32_t)bpdc::kLdsHead + ((uint32_t)g.m + 1u) * 16u;
   std::vector<int32_t> vell((size_t)std::max(1, d.max_col_deg) * g.n, (int32_t)(((uint32_t)g.m + rec0) << 10)),
@@ -948,13 +995,14 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
   for (int v = 0; v < g.n; ++v)
     for (int k = cp[v]; k < cp[v + 1]; ++k) {
       const int edge = ce[k], r = er[edge];
-      vell[(size_t)(k - cp[v]) * g.n + v] = (int32_t)((((uint32_t)r + rec0) << 10) | (uint32_t)(edge - hrp[r]));
+      vell[(size_t)(k - cp[v]) * g.n + col_slot[v]] =
+          (int32_t)((((uint32_t)r + rec0) << 10) | (uint32_t)(edge - hrp[r]));
     }
   for (int r = 0; r < g.m; ++r)
     for (int k = hrp[r]; k < hrp[r + 1]; ++k)
-      cell[(size_t)(k - hrp[r]) * g.m + r] = (int32_t)(l_off + 4u * (uint32_t)hci[k]);
+      cell[(size_t)(k - hrp[r]) * g.m + r] = (int32_t)(l_off + 4u * (uint32_t)col_slot[hci[k]]);
   std::vector<int32_t> vblk((size_t)std::max(1, (g.n + 63) / 64), 0);
-  for (int v = 0; v < g.n; ++v) vblk[v >> 6] = std::max(vblk[v >> 6], cp[v + 1] - cp[v]);
+  for (int v = 0; v < g.n; ++v) vblk[col_slot[v] >> 6] = std::max(vblk[col_slot[v] >> 6], cp[v + 1] - cp[v]);
   if (hipGetDevice(&c->device) != hipSuccess) return fail(BPDC_ERR_HIP, "no HIP device");
   hipError_t e;
   if ((e = upload(&d.h_row_ptr, hrp)) != hipSuccess || (e = upload(&d.h_col, hci)) != hipSuccess ||
@@ -962,7 +1010,8 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
       (e = upload(&d.h_edge_row, er)) != hipSuccess || (e = upload(&d.d_row_ptr, drp)) != hipSuccess ||
       (e = upload(&d.d_col, dci)) != hipSuccess || (e = upload(&d.lam, c->lam)) != hipSuccess ||
       (e = upload(&d.v_ell, vell)) != hipSuccess || (e = upload(&d.c_ell, cell)) != hipSuccess ||
-      (e = upload(&d.v_blk_deg, vblk)) != hipSuccess) {
+      (e = upload(&d.v_blk_deg, vblk)) != hipSuccess || (e = upload(&d.g_lam, glam)) != hipSuccess ||
+      (e = upload(&d.g_dcol, gdcol)) != hipSuccess || (e = upload(&d.g_pos, col_slot)) != hipSuccess) {
     bpdc_code_destroy(c.release());
     return fail(e == hipErrorOutOfMemory ? BPDC_ERR_OOM : BPDC_ERR_HIP, "upload: %s", hipGetErrorString(e));
   }
@@ -973,8 +1022,8 @@ bpdc_status bpdc_code_create(const bpdc_csr* H, const bpdc_csr* D, const double*
 bpdc_status bpdc_code_destroy(bpdc_code c) {
   if (!c) return BPDC_OK;
   bpdc::DevCode& d = c->dev;
-  void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row,
-                  d.d_row_ptr, d.d_col,     d.lam,       d.v_ell,      d.c_ell, d.v_blk_deg};
+  void* ptrs[] = {d.h_row_ptr, d.h_col, d.h_col_ptr, d.h_col_edge, d.h_edge_row, d.d_row_ptr, d.d_col,
+                  d.lam,       d.v_ell, d.c_ell,     d.v_blk_deg,  d.g_lam,      d.g_dcol,    d.g_pos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
