@@ -143,9 +143,13 @@ bpdc_status bpdc_code_info(bpdc_code code, int32_t* n, int32_t* m, int32_t* md, 
  *    a wave stages in LDS (8, 16 or 32), each a code-specialised compile
  *    (cached on disk; bpdc_lane_precompile fills the cache);
  *  - group family: threads per workgroup (64 ... 1024, one shot per
- *    workgroup, its state in LDS);
+ *    workgroup, its state in LDS), ranked on a batch in which every shot
+ *    runs min(16, T) iterations per pass without early stop (so that a few
+ *    long shots of a short batch cannot turn the time into one shot's
+ *    latency);
  *  - AUTO: when both fused families can run a code, both are tuned and the
- *    faster per shot is kept; otherwise the one that can (else plain);
+ *    faster per shot is kept (the group tile chosen as above, timed again
+ *    with the plan's iterations); otherwise the one that can (else plain);
  *  - the multi-code launch (more than one code): threads per workgroup timed
  *    on a synthetic mixed batch of every code.
  * bpdc_plan_describe reports the choices and the timings.
