@@ -49,6 +49,27 @@ def test_group_kernel_bit_exact(P, name):
     assert_bit_exact(g, ref, code.n)
 
 
+# one-wave workgroups on a code of more than 32 checks and 32 columns per thread (phenomenological
+# BB144, T = 30: 2160 x 6480): the stop test reads the syndrome bits from LDS instead of a register
+# and the second pass under the channel prior takes the variable phase that tests each column's cut
+# bit; 1024 threads take the register paths on the same shots; both bit-exact with the oracle
+@pytest.mark.parametrize("threads", [64, 1024])
+def test_group_kernel_one_wave_workgroups_on_a_large_code(P, monkeypatch, threads):
+    code = synth.phenomenological_dem(synth.bb_code("bb144"), 30, 0.01, 0.01, False)
+    assert code.H.rows > 32 * 64 and code.n > 32 * 64 and code.H.rows <= 32 * 1024
+    monkeypatch.setenv("BPDC_GROUP_THREADS", str(threads))
+    shots = synth.make_shots(code, 200, 77)
+    prm = P.Params(max_iter=(30, 30), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=9)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    print(f"case group {threads} threads n={code.n} m={code.H.rows} tile={plan.info(0)}", flush=True)
+    assert plan.info(0)["threads"] == threads
+    g = gpu_decode(plan, code, shots.syndromes, shot_offset=3)
+    ref = oracle.decode(code, shots.syndromes, oracle_params(prm, code.second_pass), precision="f32",
+                        shot_offset=3)
+    assert ((ref["flags"] & 2) != 0).sum() > 0
+    assert_bit_exact(g, ref, code.n)
+
+
 # single-code launches of small codes claim several consecutive shots at a time (toric L = 6,
 # 72 columns: 8): one shot, batches that end inside the first claim or just past it, and a batch
 # whose last claim straddles its end, all bit-exact at a nonzero shot offset
