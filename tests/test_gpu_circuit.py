@@ -47,6 +47,28 @@ def test_circuit_dem_bit_exact_vs_float32_oracle(P, kernel, name, rounds, p, sho
     assert_bit_exact(g, ref, code.n)
 
 
+# rows of 35 edges: the 64-bit-record variant keeps posteriors, priors and rows of D in slots
+# sorted by column degree; the posterior second pass (its prior array in slot order, +inf on the
+# cut) and intermittent soft DC (the nominees' priors raised in slot order), posteriors and cut
+# masks included, bit-exact with the oracle
+@pytest.mark.parametrize("mode", ["posterior", "soft"])
+def test_circuit_dem_group_posterior_prior_and_soft_dc(P, mode):
+    code = synth.bb_circuit_dem("bb72", 3, 0.004)
+    sh = synth.make_shots(code, 400, 8400)
+    if mode == "posterior":
+        prm = P.Params(max_iter=(60, 60), alpha=0.625, second_pass_prior=P.PRIOR_POSTERIOR, seed=19)
+    else:
+        prm = P.Params(max_iter=(60, 60), alpha=0.625, second_pass_prior=P.PRIOR_CHANNEL, seed=19,
+                       soft_period=5, soft_shift=0.5)
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=P.KERNEL_GROUP)
+    print(f"case circuit bb72 T=3 group {mode}", flush=True)
+    g = gpu_decode(plan, code, sh.syndromes, shot_offset=5)
+    ref = oracle.decode(code, sh.syndromes, oracle_params(prm, "posterior" if mode == "posterior" else "channel"),
+                        precision="f32", shot_offset=5)
+    assert ((ref["flags"] & 2) != 0).sum() > 10, "case must exercise DC"
+    assert_bit_exact(g, ref, code.n)
+
+
 def test_circuit_plan_choice(P):
     code = P.Code.from_problem(synth.bb_circuit_dem("bb72", 2, 0.002))
     prm = _params(P, (50, 50))
