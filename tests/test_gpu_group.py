@@ -163,6 +163,21 @@ def test_multi_code_single_launch_bit_exact(P):
     _check_multi(P, prm, codes, per_code, outs[0], corr_off)
 
 
+# a circuit-level DEM (rows of 35: 64-bit check records, posteriors in slots sorted by column
+# degree) in one launch with codes of rows of at most 32 edges (column order), all run by the
+# 64-bit-record variant
+def test_multi_code_mixed_record_widths_bit_exact(P):
+    codes = [synth.bb_circuit_dem("bb72", 2, 0.003), synth.bb_code("bb144", p=0.05), _small_hgp(1, 20, p=0.05)]
+    counts = [40, 60, 50]
+    prm = P.Params(max_iter=(60, 60), alpha=0.625, seed=4)
+    plan = P.Plan([P.Code.from_problem(c) for c in codes], prm, kernel=P.KERNEL_GROUP)
+    code_of_shot, syn, per_code = _mixed_batch(P, codes, counts, 80)
+    print("case multi-code circuit bb72 + bb144 + hgp20", flush=True)
+    outs, corr_off = _run_multi(P, plan, codes, code_of_shot, syn)
+    assert (outs[0][1] & 2).any(), "case must exercise DC"
+    _check_multi(P, prm, codes, per_code, outs[0], corr_off)
+
+
 def test_multi_code_graph_replays(P):
     codes = [_small_hgp(j, nc, p=0.05) for j, nc in enumerate([16, 24])]
     counts = [70, 50]
