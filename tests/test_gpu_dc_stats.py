@@ -89,14 +89,18 @@ KERNELS = {"lane": "KERNEL_LANE", "plain": "KERNEL_PLAIN", "group": "KERNEL_GROU
 
 
 def _code(name, p):
+    if name == "circuit_bb72":  # rows of 35: the group kernel's 64-bit records, slots sorted by degree
+        return synth.bb_circuit_dem("bb72", 3, p)
     return synth.toric_code(3, p=p) if name == "toric3" else synth.bb_code(name, p=p)
 
 
 # toric L = 3 (9 checks): too small for the group kernel's in-LDS histogram, which then adds to the
 # device histogram row by row
-@pytest.mark.parametrize("kernel", ["lane", "plain", "group"])
-@pytest.mark.parametrize("name,p,shots,T", [("bb144", 0.05, 3000, (100, 100)), ("bb72", 0.06, 2000, (40, 40)),
-                                            ("toric3", 0.08, 3000, (18, 18))])
+@pytest.mark.parametrize("kernel,name,p,shots,T",
+                         [(k, *case) for k in ("lane", "plain", "group")
+                          for case in (("bb144", 0.05, 3000, (100, 100)), ("bb72", 0.06, 2000, (40, 40)),
+                                       ("toric3", 0.08, 3000, (18, 18)))]
+                         + [(k, "circuit_bb72", 0.004, 1000, (60, 60)) for k in ("plain", "group")])
 def test_min_sum_dc_stats_vs_float32_oracle(P, kernel, name, p, shots, T):
     import torch
     code = _code(name, p)
