@@ -2,8 +2,9 @@
 (needs an MI355X): H rows of 64 edges, H columns of 16, D rows of 32, the group
 family's rows of 58 (64-bit check records) and 32 (the widest 32-bit records),
 product-sum rows of 8 on the group family; one past each limit is refused with
-BpdcError.  Min-sum outputs bit-exact with the float32 oracle; product-sum on
-the group family bit-identical with the plain family.
+BpdcError; and at the other end codes with checks and columns that have no
+edges, or no edge at all.  Min-sum outputs bit-exact with the float32 oracle;
+product-sum on the group family bit-identical with the plain family.
 
 The codes are synthetic: every column meets `dv` distinct checks, chosen among
 the checks of lowest current degree (random order among equals), so with
@@ -145,3 +146,38 @@ def test_product_sum_row_limits(P):
     over = P.Code.from_problem(_code(12, 33, 3, [4], 0.02, 111))
     with pytest.raises(P.BpdcError):
         P.Plan([over], prm, kernel=P.KERNEL_PLAIN)
+
+
+def _degenerate(case, seed=5):
+    rng = np.random.default_rng(seed)
+    if case == "no_edges":
+        m, n = 8, 16
+        H = np.zeros((m, n), np.uint8)
+    else:
+        m, n = 24, 40
+        H = (rng.random((m, n)) < 0.15).astype(np.uint8)
+        H[[0, 5], :] = 0
+        H[:, [3, 17, 39]] = 0
+    D = np.zeros((10, n), np.uint8)
+    for i in range(10):
+        D[i, rng.choice(n, size=int(rng.integers(3, 7)), replace=False)] = 1
+    return synth.Code(f"degenerate_{case}", synth.Csr.from_dense(H), synth.Csr.from_dense(D), np.full(n, 0.05), None,
+                      "channel")
+
+
+# degenerate codes: checks without edges (unsatisfiable when their syndrome bit is 1, so such shots
+# run both passes and DC) and columns without checks (their posterior stays the prior), and an H
+# without any edge; random syndromes, every output bit-exact with the float32 oracle
+@pytest.mark.parametrize("kernel", ["group", "plain", "lane"])
+@pytest.mark.parametrize("case", ["some_empty", "no_edges"])
+def test_rows_and_columns_without_edges(P, kernel, case):
+    code = _degenerate(case)
+    syn = (np.random.default_rng(7).random((300, code.m)) < 0.3).astype(np.uint8)
+    prm = _min_sum(P, T=(20, 20), seed=3)
+    kid = {"group": P.KERNEL_GROUP, "plain": P.KERNEL_PLAIN, "lane": P.KERNEL_LANE}[kernel]
+    plan = P.Plan([P.Code.from_problem(code)], prm, kernel=kid)
+    print(f"case degenerate {case} kernel={kernel} tile={plan.info(0)}", flush=True)
+    g = gpu_decode(plan, code, syn, shot_offset=2)
+    ref = oracle.decode(code, syn, oracle_params(prm, "channel"), precision="f32", shot_offset=2)
+    assert ((ref["flags"] & 2) != 0).sum() > 0 and ((ref["flags"] & 1) != 0).sum() > 0
+    assert_bit_exact(g, ref, code.n)
