@@ -151,7 +151,7 @@ bpdc_status bpdc_code_info(bpdc_code code, int32_t* n, int32_t* m, int32_t* md, 
  *    faster per shot is kept (the group tile chosen as above, timed again
  *    with the plan's iterations); otherwise the one that can (else plain);
  *  - the multi-code launch (more than one code): threads per workgroup timed
- *    on a synthetic mixed batch of every code.
+ *    on a synthetic mixed batch of every code, ranked the same way.
  * bpdc_plan_describe reports the choices and the timings.
  * BPDC_ERR_UNSUPPORTED if the requested variant cannot run a code. */
 bpdc_status bpdc_plan_create(const bpdc_code* codes, int32_t ncodes, const bpdc_params* params,

@@ -763,7 +763,7 @@ size_t multi_ws_bytes(const bpdc_plan_s* p, int64_t B) {
 bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* syn, const int64_t* syn_off,
                           uint64_t* corr, const int64_t* corr_off, uint8_t* flags, int16_t* iters, int64_t B,
                           int64_t shot_offset, void* ws, hipStream_t s, const bpdc::GroupTile* tile = nullptr,
-                          unsigned long long* dcstats = nullptr) {
+                          unsigned long long* dcstats = nullptr, const bpdc::KParams* kp = nullptr) {
   const bpdc::GroupTile& t = tile ? *tile : p->multi_tile;
   char* w = (char*)ws;
   unsigned long long* queue = (unsigned long long*)w;
@@ -771,7 +771,8 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
   unsigned* base = (unsigned*)(w + 256 + align256((p->codes.size() + 1) * 4));
   int32_t* order = (int32_t*)(w + 256 + 2 * align256((p->codes.size() + 1) * 4));
   HIP_TRY(bpdc::group_order(cos, B, p->d_code_by_rank, (int)p->codes.size(), hist, base, order, flags, s));
-  HIP_TRY(bpdc::group_launch(p->d_code_table, hist + p->codes.size(), cos, order, p->kp, syn, syn_off, corr, corr_off, flags, nullptr,
+  HIP_TRY(bpdc::group_launch(p->d_code_table, hist + p->codes.size(), cos, order, kp ? *kp : p->kp, syn, syn_off, corr,
+                             corr_off, flags, nullptr,
                              nullptr, iters, B, shot_offset, t.threads, t.grid, t.lds_bytes, t.info_bytes, queue, s,
                              dcstats));
   return BPDC_OK;
@@ -779,8 +780,9 @@ bpdc_status multi_enqueue(bpdc_plan_s* p, const int32_t* cos, const uint64_t* sy
 
 // Threads per workgroup of the multi-code launch: each candidate is timed on a
 // synthetic mixed batch (32 shots of every code drawn from its priors, codes
-// interleaved) and the fastest kept.  The LDS per workgroup is the largest
-// code's state either way.
+// interleaved; every shot runs min(16, T) iterations per pass without early
+// stop, as for a single code's group tile) and the fastest kept.  The LDS per
+// workgroup is the largest code's state either way.
 bpdc_status choose_multi_tile(bpdc_plan_s* p, const bpdc::GroupTile& base, const std::vector<int>& cands) {
   const int nc = (int)p->codes.size();
   const int per = 32;
@@ -824,6 +826,10 @@ bpdc_status choose_multi_tile(bpdc_plan_s* p, const bpdc::GroupTile& base, const
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
+  bpdc::KParams kt = p->kp;
+  kt.stop = 0;
+  kt.T1 = std::min(kt.T1, 16);
+  kt.T2 = std::min(kt.T2, 16);
   double best = -1.0;
   p->multi_tried.clear();
   for (int th : cands) {
@@ -837,7 +843,7 @@ bpdc_status choose_multi_tile(bpdc_plan_s* p, const bpdc::GroupTile& base, const
       (void)hipEventRecord(e0, 0);
       const bpdc_status st = multi_enqueue(p, (const int32_t*)d.p[0], (const uint64_t*)d.p[3], (const int64_t*)d.p[1],
                                            (uint64_t*)d.p[4], (const int64_t*)d.p[2], (uint8_t*)d.p[5], nullptr, B, 0,
-                                           d.p[6], 0, &t);
+                                           d.p[6], 0, &t, nullptr, &kt);
       (void)hipEventRecord(e1, 0);
       if (st != BPDC_OK || hipEventSynchronize(e1) != hipSuccess) {
         ms = -1.0f;
@@ -846,7 +852,8 @@ bpdc_status choose_multi_tile(bpdc_plan_s* p, const bpdc::GroupTile& base, const
       (void)hipEventElapsedTime(&ms, e0, e1);
     }
     TuneTry tt;
-    tt.what = "multi-code " + std::to_string(th) + " threads, " + std::to_string(nb) + " workgroups/CU";
+    tt.what = "multi-code " + std::to_string(th) + " threads, " + std::to_string(nb) +
+              " workgroups/CU (16 + 16 iterations, no early stop)";
     tt.ms_per_kshot = ms > 0 ? ms * 1000.0 / (double)B : -1.0;
     p->multi_tried.push_back(tt);
     if (ms > 0 && (best < 0 || tt.ms_per_kshot < best)) {
