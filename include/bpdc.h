@@ -165,8 +165,10 @@ bpdc_status bpdc_plan_info(bpdc_plan plan, int32_t code, int32_t* kernel, int32_
 /* The autotuner's record for code `code` (or, with code = -1, the multi-code
  * launch) as a JSON object written to buf (host, cap bytes, NUL-terminated,
  * truncated to fit): the family and tile kept, why, and every candidate timed
- * with its time per 1000 synthetic shots.  *needed (optional) gets the full
- * length + 1. */
+ * with its time per 1000 synthetic shots (group and multi-code candidates on
+ * the fixed-iteration batch; under AUTO, one more group entry: the chosen
+ * tile with the plan's iterations).  *needed (optional) gets the full length
+ * + 1. */
 bpdc_status bpdc_plan_describe(bpdc_plan plan, int32_t code, char* buf, size_t cap, size_t* needed);
 
 /* Diagnostics of degeneracy cutting (Appendix B: how flat are the posterior
